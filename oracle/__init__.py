@@ -1,0 +1,262 @@
+"""CPU FP64 oracle of the radiative-transfer step (Jiang, Stone & Davis 2014).
+
+TEST INFRASTRUCTURE ONLY.  Only the tests, the smoke check and the CPU
+baseline leg of the benchmark may import this package.  It shares no code
+with the GPU library (``paper_1403_6126_amd``): it has its own C step
+(``rt_oracle.c``), its own quadrature (``quadrature.py``) and its own dense
+brute-force solvers (``dense.py``).  The only shared module is the seeded
+input generator ``workloads``.
+"""
+from __future__ import annotations
+
+import ctypes as ct
+import os
+import subprocess
+import sysconfig
+
+import numpy as np
+
+from .quadrature import angle_set, gauss_legendre, level_symmetric  # noqa: F401
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "rt_oracle.c")
+_LIB = os.path.join(_HERE, "_rt_oracle.so")
+NTOT = 12
+FOUR_PI = 4.0 * np.pi
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle's C step with gcc (-O2, no fast-math, OpenMP)."""
+    if force or not os.path.exists(_LIB):
+        tmp = _LIB + ".tmp"
+        cmd = ["gcc", "-O2", "-std=c11", "-D_DEFAULT_SOURCE", "-fopenmp", "-fPIC",
+               "-shared", "-Wall", "-o", tmp, _SRC, "-lm"]
+        subprocess.run(cmd, check=True)
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+class _Problem(ct.Structure):
+    _fields_ = [
+        ("ndim", ct.c_int), ("n", ct.c_int * 3), ("dx", ct.c_double * 3),
+        ("bc", (ct.c_int * 2) * 3), ("nang", ct.c_int),
+        ("mu", ct.POINTER(ct.c_double)), ("w", ct.POINTER(ct.c_double)),
+        ("ghost", (ct.POINTER(ct.c_double) * 2) * 3),
+        ("C", ct.c_double), ("P", ct.c_double), ("gamma", ct.c_double), ("R", ct.c_double),
+        ("estimate_v", ct.c_int), ("rtol", ct.c_double), ("maxit", ct.c_int),
+    ]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build(force=False)
+        L = ct.CDLL(_LIB)
+        dp = ct.POINTER(ct.c_double)
+        pp = ct.POINTER(_Problem)
+        L.or_moments.argtypes = [pp, dp, dp, dp, dp]
+        L.or_transport.argtypes = [pp, ct.c_double, dp, dp, dp, dp, dp, dp]
+        L.or_vtilde.argtypes = [pp, ct.c_double, dp, dp, dp, dp, dp, dp, dp, dp]
+        L.or_absorption_cell.argtypes = [pp, ct.c_double, ct.c_double, ct.c_double, dp, dp,
+                                         ct.c_double, dp, dp]
+        L.or_absorption_cell.restype = ct.c_int
+        L.or_scattering_cell.argtypes = [pp, ct.c_double, ct.c_double, dp, dp, dp]
+        L.or_scattering_cell.restype = ct.c_int
+        L.or_step.argtypes = [pp, ct.c_double, dp, dp, dp, dp, dp, dp, dp, dp, dp, dp, dp,
+                              dp, dp, ct.c_int]
+        L.or_step.restype = ct.c_int
+        L.or_step_cells.argtypes = [pp, ct.c_double, dp, dp, dp, dp, dp, dp, ct.c_int,
+                                    ct.POINTER(ct.c_longlong), dp, dp, dp, dp, dp, dp, dp,
+                                    dp]
+        L.or_step_cells.restype = ct.c_int
+        L.or_totals.argtypes = [pp, dp, dp, dp, dp, dp, dp, dp, dp, dp]
+        L.or_threads.restype = ct.c_int
+        _lib = L
+    return _lib
+
+
+def _dp(a):
+    if a is None:
+        return None
+    assert a.dtype == np.float64 and a.flags["C_CONTIGUOUS"], "need contiguous float64"
+    return a.ctypes.data_as(ct.POINTER(ct.c_double))
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+class Problem:
+    """Problem description for the oracle (grid, angles, parameters)."""
+
+    def __init__(self, wl, mu=None, w=None, estimate_v: bool = True,
+                 rtol: float = 1e-14, maxit: int = 64, ghost=None):
+        if mu is None:
+            mu, w = angle_set(wl.quad)
+        self.wl = wl
+        self.mu = _f64(mu)
+        self.w = _f64(w)
+        self.nang = self.w.shape[0]
+        self._keep = []
+        s = _Problem()
+        s.ndim = wl.ndim
+        for d in range(3):
+            s.n[d] = wl.n[d]
+            s.dx[d] = wl.dx[d]
+            for side in range(2):
+                s.bc[d][side] = wl.bc[d][side]
+        s.nang = self.nang
+        s.mu = _dp(self.mu)
+        s.w = _dp(self.w)
+        if ghost is None and wl.ghost is not None:
+            ghost = wl.ghost(self.mu)
+        for d in range(3):
+            for side in range(2):
+                if ghost is not None and (d, side) in ghost:
+                    g = _f64(ghost[(d, side)])
+                    self._keep.append(g)
+                    s.ghost[d][side] = _dp(g)
+        s.C, s.P, s.gamma, s.R = wl.C, wl.P, wl.gamma, wl.R
+        s.estimate_v = 1 if estimate_v else 0
+        s.rtol = rtol
+        s.maxit = maxit
+        self.s = s
+
+    @property
+    def ptr(self):
+        return ct.byref(self.s)
+
+
+def moments(prob: Problem, I):
+    nc = prob.wl.ncell
+    E = np.empty(nc)
+    F = np.empty((3, nc))
+    Pr = np.empty((6, nc))
+    lib().or_moments(prob.ptr, _dp(_f64(I)), _dp(E), _dp(F), _dp(Pr))
+    return E, F, Pr
+
+
+def transport(prob: Problem, dt, I, J, v, sa, ss):
+    nc = prob.wl.ncell
+    dF = np.empty((prob.nang, nc))
+    lib().or_transport(prob.ptr, dt, _dp(_f64(I)), _dp(_f64(J)), _dp(_f64(v)),
+                       _dp(_f64(sa)), _dp(_f64(ss)), _dp(dF))
+    return dF
+
+
+def vtilde(prob: Problem, dt, rho, sa, ss, v, E, F, Pr):
+    nc = prob.wl.ncell
+    out = np.empty((3, nc))
+    lib().or_vtilde(prob.ptr, dt, _dp(_f64(rho)), _dp(_f64(sa)), _dp(_f64(ss)), _dp(_f64(v)),
+                    _dp(_f64(E)), _dp(_f64(F)), _dp(_f64(Pr)), _dp(out))
+    return out
+
+
+def absorption_cell(prob: Problem, dt, sa, rho, u, r, Tn):
+    Iout = np.empty(prob.nang)
+    Tout = np.empty(1)
+    it = lib().or_absorption_cell(prob.ptr, dt, sa, rho, _dp(_f64(u)), _dp(_f64(r)), Tn,
+                                  _dp(Iout), _dp(Tout))
+    return Iout, float(Tout[0]), it
+
+
+def scattering_cell(prob: Problem, dt, ss, u, r):
+    Iout = np.empty(prob.nang)
+    st = lib().or_scattering_cell(prob.ptr, dt, ss, _dp(_f64(u)), _dp(_f64(r)), _dp(Iout))
+    if st != 0:
+        raise RuntimeError("singular scattering matrix")
+    return Iout
+
+
+def totals(prob: Problem, rho, T, E, F, dEgas=None, dEkin=None, dMom=None, I=None):
+    out = np.empty(NTOT)
+    lib().or_totals(prob.ptr, _dp(_f64(rho)), _dp(_f64(T)), _dp(_f64(E)), _dp(_f64(F)),
+                    _dp(None if dEgas is None else _f64(dEgas)),
+                    _dp(None if dEkin is None else _f64(dEkin)),
+                    _dp(None if dMom is None else _f64(dMom)),
+                    _dp(None if I is None else _f64(I)), _dp(out))
+    return out
+
+
+class State:
+    """Evolving oracle state: I (nang, ncell), T, last moments and the
+    accumulated gas source terms of the steps taken so far."""
+
+    def __init__(self, prob: Problem, I0=None, T0=None):
+        wl = prob.wl
+        self.prob = prob
+        self.I = _f64(wl.init(prob.mu) if I0 is None else I0).copy()
+        self.T = _f64(wl.T if T0 is None else T0).copy()
+        nc = wl.ncell
+        self.dEgas = np.zeros(nc)
+        self.dEkin = np.zeros(nc)
+        self.dMom = np.zeros((3, nc))
+        self.E, self.F, self.Pr = moments(prob, self.I)
+        self.newton_max = 0
+        self.steps = 0
+
+    def step(self, dt=None, nsteps: int = 1):
+        p = self.prob
+        wl = p.wl
+        dt = wl.dt if dt is None else dt
+        rho, sa, ss, v = _f64(wl.rho), _f64(wl.sigma_a), _f64(wl.sigma_s), _f64(wl.v)
+        out = np.empty_like(self.I)
+        for _ in range(nsteps):
+            it = lib().or_step(p.ptr, dt, _dp(rho), _dp(sa), _dp(ss), _dp(v), _dp(self.I),
+                               _dp(out), _dp(self.T), _dp(self.dEgas), _dp(self.dEkin),
+                               _dp(self.dMom), _dp(self.E), _dp(self.F), _dp(self.Pr),
+                               1 if self.steps > 0 else 0)
+            if it < 0:
+                raise RuntimeError("oracle Newton iteration did not converge")
+            self.newton_max = max(self.newton_max, it)
+            self.I, out = out, self.I
+            self.steps += 1
+        return self
+
+    def totals(self):
+        wl = self.prob.wl
+        return totals(self.prob, wl.rho, self.T, self.E, self.F, self.dEgas, self.dEkin,
+                      self.dMom, self.I)
+
+
+def run(wl, nsteps=None, mu=None, w=None, I0=None, T0=None, **kw) -> State:
+    prob = Problem(wl, mu, w, **kw)
+    st = State(prob, I0, T0)
+    st.step(nsteps=wl.nsteps if nsteps is None else nsteps)
+    return st
+
+
+def step_cells(prob: Problem, I, T, cells, dt=None):
+    """One step evaluated only at the given cells (for sampled comparisons at
+    sizes where the whole-domain oracle is too slow).  Returns a dict of the
+    per-cell results, each indexed like ``cells``."""
+    wl = prob.wl
+    dt = wl.dt if dt is None else dt
+    nc = wl.ncell
+    cells = np.ascontiguousarray(cells, dtype=np.int64)
+    I_out = np.zeros((prob.nang, nc))
+    T_out = np.zeros(nc)
+    dEgas = np.zeros(nc)
+    dEkin = np.zeros(nc)
+    dMom = np.zeros((3, nc))
+    E = np.zeros(nc)
+    F = np.zeros((3, nc))
+    Pr = np.zeros((6, nc))
+    it = lib().or_step_cells(prob.ptr, dt, _dp(_f64(wl.rho)), _dp(_f64(wl.sigma_a)),
+                             _dp(_f64(wl.sigma_s)), _dp(_f64(wl.v)), _dp(_f64(I)),
+                             _dp(_f64(T)), len(cells),
+                             cells.ctypes.data_as(ct.POINTER(ct.c_longlong)), _dp(I_out),
+                             _dp(T_out), _dp(dEgas), _dp(dEkin), _dp(dMom), _dp(E), _dp(F),
+                             _dp(Pr))
+    if it < 0:
+        raise RuntimeError("oracle Newton iteration did not converge")
+    return dict(I=I_out[:, cells], T=T_out[cells], dEgas=dEgas[cells], dEkin=dEkin[cells],
+                dMom=dMom[:, cells], E=E[cells], F=F[:, cells], Pr=Pr[:, cells])
+
+
+def threads() -> int:
+    return int(lib().or_threads())
