@@ -1,0 +1,190 @@
+"""Benchmark of the fused radiative-transfer step on one MI355X.
+
+Workload: 3D periodic box 128^3, 80 directions (level-symmetric S8), FP64
+intensities, rho lognormal(1), T lognormal(0.3), v Gaussian (rms 0.02 c per
+component), sigma_a = 0.1 rho, sigma_s = rho, dt at Courant 0.4; the same box
+is also timed with FP32 intensities and FP64 temperature solve.  A step is
+one fused launch doing transport, velocity estimate, absorption, scattering
+and quadrature for every cell and angle, plus the small reduction of the
+domain totals.  Inputs are resident in device memory before timing starts.
+
+Prints one JSON line (rank 0): the FP64 throughput in cell-angle updates/s,
+the roofline of the fused kernel (algorithmic bytes per launch over the mean
+launch time from HIP events recorded around each launch on its stream), the
+FP32-mixed throughput, and the CPU oracle's rate on a bounded sample.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "cell-angle updates/s, FP64 vs FP32-mixed; p50/p99 latency of served solves"
+HBM_PEAK_GBS = 8000.0
+FIELD_BYTES_PER_CELL = 232  # 14 FP64 per-cell reads + 15 FP64 per-cell writes
+
+
+def algorithmic_bytes_per_cell(nang: int, sbytes: int) -> int:
+    """I read once and written once per angle, plus the per-cell fields."""
+    return 2 * sbytes * nang + FIELD_BYTES_PER_CELL
+
+
+def load_traffic(kernel: str, workload: str):
+    """HBM bytes per launch measured with rocprofv3 counters, if a summary for
+    this kernel and workload is committed under profiles/."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{kernel}_{workload}.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        with open(path) as f:
+            d = json.load(f)
+        return d.get("bytes_per_launch")
+    except Exception:
+        return None
+
+
+def run_gpu(wl, precision: str, steps: int, warmup: int):
+    import torch
+
+    import workloads as W
+    from paper_1403_6126_amd import rt
+    from paper_1403_6126_amd.solver import Solver, quadrature_for
+
+    mu, w = quadrature_for(wl.quad)
+    T = torch.as_tensor(wl.T).cuda()
+    I0 = W.equilibrium_intensity(T, len(w), xp=torch)
+    s = Solver(wl, precision=precision, mu=mu, w=w, I0=I0)
+    del I0
+    info = rt.rt_get_info(s.ctx)
+    stream = torch.cuda.current_stream().cuda_stream
+    if warmup:
+        rt.rt_step(s.ctx, wl.dt, warmup, s.fields, s.out, stream)
+    torch.cuda.synchronize()
+    rt.rt_profile_read(s.ctx)  # discard
+    rt.rt_profile_enable(s.ctx, True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    rt.rt_step(s.ctx, wl.dt, steps, s.fields, s.out, stream)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    kms, nl = rt.rt_profile_read(s.ctx)
+    rt.rt_profile_enable(s.ctx, False)
+    status = s.status()
+    totals = s.totals.cpu().tolist()
+    s.close()
+    if status != 0:
+        raise RuntimeError(f"device status {status} after the timed steps")
+    wall = t1 - t0
+    upd = wl.ncell * info.nang * steps
+    kavg = kms / max(nl, 1) / 1e3
+    bpl = algorithmic_bytes_per_cell(info.nang, info.storage_bytes) * wl.ncell
+    return dict(value=upd / wall, ms_per_step=wall / steps * 1e3, kernel_ms=kavg * 1e3,
+                launches=nl, bytes_per_launch=bpl, achieved_gbs=bpl / kavg / 1e9,
+                nang=info.nang, storage_bytes=info.storage_bytes, totals=totals,
+                grid_blocks=info.grid_blocks, block_threads=info.block_threads)
+
+
+def cpu_baseline(wl, budget_s: float = 12.0, batch: int = 65536, seed: int = 0):
+    """The CPU oracle (as it stands) on a bounded sample of the same workload:
+    one step evaluated on batches of random cells of the 128^3 box until the
+    time budget is spent."""
+    import numpy as np
+
+    import oracle
+
+    prob = oracle.Problem(wl)
+    I = wl.init(prob.mu)
+    rng = np.random.default_rng(seed)
+    done = 0
+    t0 = time.perf_counter()
+    while time.perf_counter() - t0 < budget_s:
+        cells = np.sort(rng.choice(wl.ncell, batch, replace=False))
+        oracle.step_cells(prob, I, wl.T, cells)
+        done += len(cells)
+    el = time.perf_counter() - t0
+    return dict(value=done * prob.nang / el, unit="cell-angle updates/s", cores=oracle.threads(),
+                kind="oracle",
+                sample=f"one step at {done} randomly sampled cells of the 128^3 S8 FP64 box "
+                       f"(batches of {batch}; each batch also takes the moments of all cells), "
+                       f"{el:.1f} s")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--nper", type=int, default=128, help="cells per axis (128 = full workload)")
+    ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-budget", type=float, default=12.0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); multi-GPU runs "
+              "are not part of this build", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import workloads as W
+
+    assert torch.cuda.is_available(), "no GPU visible"
+    torch.cuda.set_device(0)
+    wl = W.config2(nper=args.nper)
+    wname = f"box3d-{args.nper}^3-S8"
+    print(f"bench: {wname} fp64 warmup={args.warmup} steps={args.steps}", file=sys.stderr,
+          flush=True)
+    r64 = run_gpu(wl, "fp64", args.steps, args.warmup)
+    print(f"bench: fp64 {r64['value']:.4g} cell-angle/s, kernel {r64['kernel_ms']:.3f} ms",
+          file=sys.stderr, flush=True)
+    mixed = None
+    if not args.no_mixed:
+        rmx = run_gpu(wl, "mixed", args.steps, args.warmup)
+        print(f"bench: mixed {rmx['value']:.4g} cell-angle/s, kernel {rmx['kernel_ms']:.3f} ms",
+              file=sys.stderr, flush=True)
+        mixed = dict(value=rmx["value"], ms_per_step=rmx["ms_per_step"], dtype="f32 (I), f64 (T)",
+                     roofline=dict(bound="hbm", achieved=rmx["achieved_gbs"], peak=HBM_PEAK_GBS,
+                                   unit="GB/s", frac=rmx["achieved_gbs"] / HBM_PEAK_GBS,
+                                   traffic=load_traffic("k_step_fused_mixed", wname),
+                                   kernel_ms=rmx["kernel_ms"],
+                                   bytes_per_launch=rmx["bytes_per_launch"]))
+    cpu = None
+    if not args.no_cpu_baseline:
+        print("bench: cpu baseline (oracle)", file=sys.stderr, flush=True)
+        cpu = cpu_baseline(wl, args.cpu_budget)
+    line = {
+        "metric": METRIC,
+        "value": r64["value"],
+        "unit": "cell-angle updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": r64["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic (seeded generator, no dataset)",
+        "config": {"workload": f"{wname} periodic, FP64 fused step (transport + velocity "
+                               "estimate + absorption + scattering + quadrature)",
+                   "grid": [args.nper] * 3, "angles": r64["nang"], "courant": 0.4,
+                   "kappa_a": 0.1, "kappa_s": 1.0, "launch": {"blocks": r64["grid_blocks"],
+                                                              "threads": r64["block_threads"]}},
+        "roofline": {"bound": "hbm", "achieved": r64["achieved_gbs"], "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": r64["achieved_gbs"] / HBM_PEAK_GBS,
+                     "traffic": load_traffic("k_step_fused_fp64", wname),
+                     "kernel": "k_step<double,double,periodic,fused>",
+                     "kernel_ms": r64["kernel_ms"], "bytes_per_launch": r64["bytes_per_launch"]},
+        "fp32_mixed": mixed,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,204 @@
+/*
+ * rt.h -- C ABI of the MI355X (gfx950) radiative-transfer step library.
+ *
+ * The library advances the frequency-integrated specific intensity
+ * I(x, n_m) on a Cartesian grid of discrete ordinates by the method of
+ * Jiang, Stone & Davis (2014, ApJS 213, 7), one time step at a time:
+ *   - explicit conservative upwind transport along every ray with
+ *     monotonic piecewise-linear (van Leer) interface values, the
+ *     optical-depth-reduced transport speed alpha*C for I - IV/C and the
+ *     flow speed for IV = 3 n.v J (Section 4.2);
+ *   - the half-step velocity estimate (Section 4.5);
+ *   - the implicit absorption step in the mixed frame to O(v/c), coupled to
+ *     the gas temperature (Section 4.3, Eq. absorptionmatrix);
+ *   - the implicit scattering step (Section 4.4);
+ *   - the angular quadrature (Section 3) giving E_r, F_r, P_r and the gas
+ *     energy and momentum source terms (Sections 4.3-4.4, Step 7).
+ * The gas (MHD) update is not part of the library: density, opacities and
+ * velocity are inputs held fixed; the gas temperature is advanced.
+ *
+ * Units are the paper's dimensionless ones (Section 2): c is Crat, prat is
+ * Prat, the equilibrium intensity is T^4/(4 pi).  Angle weights sum to 1,
+ * so E_r = 4 pi sum W I, F_r = 4 pi sum W n I, P_r = 4 pi sum W n n I.
+ *
+ * Memory layout (all device arrays are caller-owned unless stated):
+ *   - cell index c = x + nx*(y + ny*z);
+ *   - per-cell scalars: [ncell] doubles;
+ *   - vectors (v, F_r, dMom): [3][ncell] doubles (component-major);
+ *   - pressure tensor P_r: [6][ncell] doubles, order xx, yy, zz, xy, xz, yz;
+ *   - intensities I and transport increments dF: [nang][ncell] in the
+ *     storage type of the context (double for RT_FP64, float for
+ *     RT_FP32_MIXED), angle-major.
+ *
+ * Calls are asynchronous on the given stream (a hipStream_t passed as a
+ * void pointer; NULL is the default stream).  A context is not thread safe:
+ * use one context per stream.  Every call returns an rt_status; device-side
+ * failures (Newton non-convergence, non-finite or non-positive temperature)
+ * set a flag that the next rt_sync_status() reports.  No exceptions cross
+ * this interface.
+ */
+#ifndef RT_H
+#define RT_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum rt_status {
+  RT_OK = 0,
+  RT_EINVAL = -1,      /* invalid argument                                  */
+  RT_ENOMEM = -2,      /* device or host allocation failed                  */
+  RT_EDEVICE = -3,     /* HIP runtime error                                 */
+  RT_ECFL = -4,        /* dt violates sum_d C |mu_d| dt / dx_d <= 1         */
+  RT_ENOCONV = -5,     /* Newton iteration of the temperature did not
+                          converge, or gave a non-positive/non-finite T     */
+  RT_EBADQUAD = -6,    /* weights do not sum to 1 or |n| != 1               */
+  RT_ESTATE = -7,      /* call order violated (e.g. no intensity bound)     */
+  RT_EUNSUPPORTED = -8 /* valid request this build does not support         */
+} rt_status;
+
+enum { RT_BC_PERIODIC = 0, RT_BC_FIXED = 1, RT_BC_COPY = 2, RT_BC_VACUUM = 3 };
+enum { RT_FP64 = 0, RT_FP32_MIXED = 1 };
+enum { RT_QUAD_GAUSS_LEGENDRE = 0, RT_QUAD_LEVEL_SYMMETRIC = 1 };
+/* Flag: use the half-step velocity estimate of Section 4.5 (default on). */
+#define RT_ESTIMATE_V 1u
+/* Number of entries of the totals vector. */
+#define RT_NTOT 12
+
+typedef struct rt_ctx rt_ctx;
+
+typedef struct rt_grid {
+  int ndim;      /* 1, 2 or 3; transport along the first ndim axes        */
+  int n[3];      /* cells per axis, >= 1; unused axes must be 1           */
+  double dx[3];  /* cell sizes (> 0 on active axes)                        */
+  int bc[3][2];  /* RT_BC_* per axis and side (0 = low face); periodic on
+                    one side requires periodic on the other               */
+} rt_grid;
+
+typedef struct rt_angles { /* host arrays, copied by rt_create */
+  int n;                   /* number of directions, 1..RT_MAX_ANGLES       */
+  const double *mu;        /* [n][3] direction cosines, |n| = 1            */
+  const double *w;         /* [n] weights > 0 with sum 1                   */
+} rt_angles;
+
+#define RT_MAX_ANGLES 1024
+
+typedef struct rt_params {
+  double c;            /* Crat > 0                                          */
+  double prat;         /* Prat >= 0                                         */
+  double gamma;        /* adiabatic index > 1                               */
+  double r_ideal;      /* ideal gas constant > 0; c_v = rho r/(gamma - 1)   */
+  int precision;       /* RT_FP64 or RT_FP32_MIXED                          */
+  unsigned flags;      /* RT_ESTIMATE_V                                     */
+  double newton_rtol;  /* relative tolerance of the temperature Newton
+                          iteration (e.g. 1e-14); <= 0 selects 1e-14        */
+  int newton_maxit;    /* iteration limit (e.g. 64); <= 0 selects 64        */
+} rt_params;
+
+typedef struct rt_fields { /* device arrays, [ncell] doubles unless noted */
+  const double *sigma_a;   /* absorption coefficient >= 0                  */
+  const double *sigma_s;   /* scattering coefficient >= 0                  */
+  const double *rho;       /* density > 0                                  */
+  double *T;               /* gas temperature, read at time n and
+                              overwritten with T^{n+1}                     */
+  const double *v;         /* [3][ncell] flow velocity (held fixed)        */
+} rt_fields;
+
+typedef struct rt_out { /* device arrays; any pointer may be NULL */
+  double *Er;           /* [ncell]    E_r of the new intensities           */
+  double *Fr;           /* [3][ncell] F_r                                  */
+  double *Pr;           /* [6][ncell] P_r                                  */
+  double *dEgas;        /* [ncell] gas energy change (internal + kinetic)
+                           summed over the steps of the call               */
+  double *dMom;         /* [3][ncell] gas momentum change, summed likewise */
+  double *totals;       /* [RT_NTOT] domain totals times the cell volume:
+                           [0] Prat sum E_r, [1] sum c_v T, [2] sum dEgas,
+                           [3] sum of the kinetic part of dEgas,
+                           [4..6] sum dMom, [7..9] (Prat/c) sum F_r,
+                           [10] min over cells and angles of I,
+                           [11] largest Newton iteration count            */
+} rt_out;
+
+/* Angle sets (host only, Section 3).  kind RT_QUAD_GAUSS_LEGENDRE: order =
+ * number of nodes (even, >= 2), directions (mu, 0, 0) for 1D slabs, weights
+ * halved to sum 1.  kind RT_QUAD_LEVEL_SYMMETRIC: order N even in [2, 16],
+ * N(N+2) directions with levels mu_i^2 = (6i - 5)/(3(N - 1)) (N = 4 gives
+ * the cosines 1/3 and 0.882 printed in Section 5.2) and permutation-class
+ * weights from the sphere averages of the symmetric even monomials.
+ * Directions are written to mu[3*i + k], weights to w[i], for at most cap
+ * directions.  Returns the number of directions, or a negative rt_status. */
+int rt_quadrature(int kind, int order, double *mu, double *w, int cap);
+
+/* Creates a context on the current HIP device: validates the grid, the angle
+ * set (sum w = 1 within 1e-12, |n| = 1 within 1e-12) and the parameters,
+ * copies the angle table to the device and allocates the library-owned
+ * scratch (double-buffered moment fields, per-block partial totals, a
+ * status word).  *out receives the context, or NULL on failure. */
+int rt_create(const rt_grid *g, const rt_angles *a, const rt_params *p, rt_ctx **out);
+
+/* Frees the context and its scratch (synchronises the device first). */
+int rt_destroy(rt_ctx *ctx);
+
+/* Binds two caller-owned device buffers of nang*ncell elements of the
+ * storage type; I_a holds the current state.  The library ping-pongs
+ * between them; rt_current_intensity tells which one is current. */
+int rt_bind_intensity(rt_ctx *ctx, void *I_a, void *I_b);
+int rt_current_intensity(rt_ctx *ctx, void **I_cur);
+
+/* Ghost intensities for an RT_BC_FIXED face: host array [nang] (beams,
+ * inflow).  Ghost zones are two cells deep and both layers take the table;
+ * the ghost values of J, v and the opacities copy the edge cell. */
+int rt_set_fixed_bc(rt_ctx *ctx, int axis, int side, const double *I_ghost);
+
+/* Angular moments of the current intensities (Section 3) into out->Er, Fr,
+ * Pr, and into the context's moment fields used by the next step. */
+int rt_moments(rt_ctx *ctx, rt_out *out, void *stream);
+
+/* Step 2 alone: writes the transport increment dF [nang][ncell] (storage
+ * type) of the current intensities for time step dt (Section 4.2). */
+int rt_transport(rt_ctx *ctx, double dt, const rt_fields *f, void *dF, void *stream);
+
+/* Steps 3-5 and 7 alone: from the current intensities and dF (NULL = no
+ * transport), computes the new intensities into the other bound buffer
+ * (which becomes current), T^{n+1}, the moments and the gas source terms of
+ * one step.  rt_transport followed by rt_source_implicit equals rt_step
+ * with nsteps = 1. */
+int rt_source_implicit(rt_ctx *ctx, double dt, const rt_fields *f, const void *dF,
+                       rt_out *out, void *stream);
+
+/* nsteps fused steps (transport, velocity estimate, absorption, scattering,
+ * quadrature; I read and written once per step).  out->dEgas and
+ * out->dMom receive the sums over the nsteps steps; the moments and totals
+ * are those after the last step. */
+int rt_step(rt_ctx *ctx, double dt, int nsteps, const rt_fields *f, rt_out *out,
+            void *stream);
+
+/* Waits for the context's work and reports (then clears) the device status:
+ * RT_OK or RT_ENOCONV. */
+int rt_sync_status(rt_ctx *ctx);
+
+/* Kernel timing: when enabled, every fused-step launch is bracketed by HIP
+ * events on its stream; rt_profile_read (which synchronises) returns the
+ * summed duration in milliseconds and the launch count since the last
+ * read, then resets them. */
+int rt_profile_enable(rt_ctx *ctx, int enable);
+int rt_profile_read(rt_ctx *ctx, double *total_ms, int *launches);
+
+/* Static description of the context: number of angles, cells, bytes per
+ * stored intensity, and the launch shape of the fused kernel. */
+typedef struct rt_info {
+  int nang;
+  long long ncell;
+  int storage_bytes;
+  int block_threads;
+  long long grid_blocks;
+} rt_info;
+int rt_get_info(rt_ctx *ctx, rt_info *info);
+
+/* Human-readable text of an rt_status. */
+const char *rt_strerror(int status);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

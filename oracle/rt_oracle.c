@@ -390,6 +390,11 @@ int or_absorption_cell(const or_problem *p, double dt, double sa, double rho,
 int or_scattering_cell(const or_problem *p, double dt, double ss,
                        const double *u, const double *r, double *Iout) {
   const int N = p->nang;
+  if (ss == 0.0) {
+    /* no scattering: M_s = diag(1/W_m), so I'_m = r_m */
+    for (int m = 0; m < N; ++m) Iout[m] = r[m];
+    return 0;
+  }
   const double C = p->C;
   const double uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
   double *A = (double *)malloc(sizeof(double) * N * N);

@@ -1,0 +1,97 @@
+"""Host-side checks of the C ABI (no GPU work): every symbol declared in
+include/rt.h is exported, the library's quadrature equals the oracle's,
+argument validation rejects bad input before touching the device, and the
+product package never reaches the oracle."""
+import ctypes as ct
+import os
+import re
+import subprocess
+
+import numpy as np
+import pytest
+
+from paper_1403_6126_amd import rt
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    txt = open(os.path.join(ROOT, "include", "rt.h")).read()
+    return sorted(set(re.findall(r"^\s*(?:int|const char \*)\s*(rt_\w+)\s*\(", txt, re.M)))
+
+
+def test_library_exports_every_declared_symbol():
+    names = _declared()
+    assert len(names) >= 15
+    L = ct.CDLL(rt.LIB_PATH)
+    for n in names:
+        assert hasattr(L, n), n
+    bound = {s[0] for s in rt.SIGNATURES}
+    assert set(names) == bound
+
+
+def test_quadrature_matches_oracle():
+    from oracle.quadrature import gauss_legendre, level_symmetric
+    for order in (2, 4, 6, 8, 10, 12):
+        mu, w = rt.rt_quadrature(rt.RT_QUAD_LEVEL_SYMMETRIC, order)
+        mo, wo = level_symmetric(order)
+        assert np.array_equal(mu, mo) or np.abs(mu - mo).max() <= 1e-15
+        assert np.abs(w - wo).max() <= 2e-15
+    for order in (14, 16):
+        mu, w = rt.rt_quadrature(rt.RT_QUAD_LEVEL_SYMMETRIC, order)
+        mo, wo = level_symmetric(order)
+        assert np.abs(mu - mo).max() <= 1e-15
+        assert np.abs(w - wo).max() <= 1e-12
+        assert abs(w.sum() - 1) <= 1e-14
+        assert np.abs(np.einsum("m,mi,mj->ij", w, mu, mu) - np.eye(3) / 3).max() <= 1e-14
+    for n in (2, 16, 64, 288):
+        mu, w = rt.rt_quadrature(rt.RT_QUAD_GAUSS_LEGENDRE, n)
+        mo, wo = gauss_legendre(n)
+        assert np.abs(mu - mo).max() <= 1e-15 and np.abs(w - wo).max() <= 1e-15
+
+
+def test_quadrature_rejects_bad_orders():
+    for kind, order in [(rt.RT_QUAD_LEVEL_SYMMETRIC, 3), (rt.RT_QUAD_LEVEL_SYMMETRIC, 18),
+                        (rt.RT_QUAD_GAUSS_LEGENDRE, 5), (7, 4)]:
+        assert rt.lib().rt_quadrature(kind, order, None, None, 0) == rt.RT_EINVAL
+
+
+def _grid():
+    return rt.make_grid(3, (4, 4, 4), (0.25, 0.25, 0.25), ((0, 0),) * 3)
+
+
+@pytest.mark.parametrize("case", ["weights", "norm", "ndim", "bc", "c", "gamma"])
+def test_create_validation_before_device(case):
+    mu, w = rt.rt_quadrature(rt.RT_QUAD_LEVEL_SYMMETRIC, 4)
+    g = _grid()
+    p = rt.make_params(1.0, 1.0, 5 / 3, 1.0)
+    expect = rt.RT_EINVAL
+    if case == "weights":
+        w = w * 1.01
+        expect = rt.RT_EBADQUAD
+    elif case == "norm":
+        mu = mu * 1.001
+        expect = rt.RT_EBADQUAD
+    elif case == "ndim":
+        g.ndim = 2                       # n[2] = 4 on an unused axis
+    elif case == "bc":
+        g.bc[0][0] = rt.RT_BC_FIXED      # periodic on one side only
+    elif case == "c":
+        p.c = 0.0
+    elif case == "gamma":
+        p.gamma = 1.0
+    with pytest.raises(rt.RTError) as ei:
+        rt.rt_create(g, mu, w, p)
+    assert ei.value.status == expect
+
+
+def test_product_package_does_not_use_oracle():
+    pkg = os.path.join(ROOT, "paper_1403_6126_amd")
+    for dirpath, _, files in os.walk(pkg):
+        for f in files:
+            if f.endswith((".py", ".hip", ".hpp", ".cpp", ".h")):
+                txt = open(os.path.join(dirpath, f)).read()
+                assert not re.search(r"^\s*(import|from)\s+oracle", txt, re.M), f
+                assert "rt_oracle" not in txt, f
+    out = subprocess.run(["ldd", rt.LIB_PATH], capture_output=True, text=True).stdout
+    assert "oracle" not in out

@@ -1,0 +1,224 @@
+"""GPU parity: the HIP library (through its C ABI) against the CPU oracle.
+
+FP64 bar: normwise relative error max|a - b| / max|b| <= 1e-12 per field
+(the vector and tensor fields over all components).  Each side uses its own
+angle table (they agree to round-off for the orders used here).
+"""
+import numpy as np
+import pytest
+
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+TOL64 = 1e-12
+
+
+def _solver(wl, **kw):
+    from paper_1403_6126_amd.solver import Solver
+    return Solver(wl, **kw)
+
+
+def _nerr(a, b):
+    den = np.abs(b).max()
+    return float(np.abs(a - b).max() / den) if den > 0 else float(np.abs(a - b).max())
+
+
+def _compare(st, ref, tol, fields=("I", "T", "E", "F", "P", "dEgas", "dMom")):
+    errs = {}
+    refmap = dict(I=ref.I, T=ref.T, E=ref.E, F=ref.F, P=ref.Pr, dEgas=ref.dEgas, dMom=ref.dMom)
+    for k in fields:
+        errs[k] = _nerr(st[k], refmap[k])
+    bad = {k: v for k, v in errs.items() if not v <= tol}
+    assert not bad, f"errors {errs}"
+    return errs
+
+
+def _run_both(wl, nsteps, precision="fp64", estimate_v=True, **kw):
+    import oracle
+    s = _solver(wl, precision=precision, estimate_v=estimate_v, **kw)
+    print(f"case {wl.name} nang={s.nang} ncell={wl.ncell} steps={nsteps} {precision}", flush=True)
+    s.step(nsteps)
+    st = s.state()
+    status = s.status()
+    s.close()
+    assert status == 0
+    ref = oracle.run(wl, nsteps=nsteps, estimate_v=estimate_v)
+    return st, ref
+
+
+def test_config1_fp64_100_steps():
+    wl = W.config1()
+    st, ref = _run_both(wl, 100)
+    _compare(st, ref, TOL64)
+    tref = ref.totals()
+    vol = wl.cell_volume
+    scale = {0: abs(tref[0]), 1: abs(tref[1]), 7: np.abs(ref.F[0]).sum() * vol,
+             2: np.abs(ref.dEgas).sum() * vol, 3: np.abs(ref.dEkin).sum() * vol}
+    for k, sc in scale.items():
+        assert abs(st["totals"][k] - tref[k]) <= 1e-12 * sc, (k, st["totals"][k], tref[k])
+
+
+def test_config2_full_size_sampled_step():
+    # 128^3, S8, FP64, the fused kernel in the benchmark's launch shape: after
+    # two GPU steps, one more GPU step is compared on sampled cells with one
+    # oracle step from the same state.
+    import oracle
+    wl = W.config2()
+    s = _solver(wl)
+    print(f"case {wl.name} full size: 2 steps, then 1 compared step", flush=True)
+    s.step(2)
+    st0 = s.state()
+    s.step(1)
+    st1 = s.state()
+    assert s.status() == 0
+    s.close()
+    rng = np.random.default_rng(123)
+    cells = np.unique(np.concatenate([rng.choice(wl.ncell, 300, replace=False),
+                                      [0, wl.ncell - 1, 127, 128 * 128 - 1]]))
+    prob = oracle.Problem(wl)
+    ref = oracle.step_cells(prob, st0["I"], st0["T"], cells)
+    del st0
+    got = dict(I=st1["I"][:, cells], T=st1["T"][cells], E=st1["E"][cells], F=st1["F"][:, cells],
+               Pr=st1["P"][:, cells], dEgas=st1["dEgas"][cells], dMom=st1["dMom"][:, cells])
+    errs = {k: _nerr(got[k], ref[k]) for k in got}
+    print("sampled errors", errs, flush=True)
+    assert max(errs.values()) <= TOL64, errs
+
+
+CASES = [
+    (1, (300,), ("gl", 8), None),
+    (2, (37, 29), ("ls", 4), None),
+    (3, (19, 13, 11), ("ls", 6), None),
+    (3, (9, 17, 5), ("ls", 8), None),
+    (2, (23, 21), ("ls", 8), ((W.BC_FIXED, W.BC_COPY), (W.BC_VACUUM, W.BC_FIXED), (0, 0))),
+    (3, (12, 10, 9), ("ls", 4), ((W.BC_FIXED, W.BC_FIXED), (W.BC_COPY, W.BC_VACUUM),
+                                 (W.BC_PERIODIC, W.BC_PERIODIC))),
+    (1, (129,), ("gl", 32), ((W.BC_VACUUM, W.BC_COPY), (0, 0), (0, 0))),
+]
+
+
+@pytest.mark.parametrize("ndim,shape,quad,bc", CASES)
+def test_small_cases_fp64(ndim, shape, quad, bc):
+    wl = W.small_case(ndim, shape, quad, seed=31 + ndim, nsteps=4, kappa_a=3.0, kappa_s=2.0,
+                      vscale=0.05, bc=bc, ghost_seed=5 if bc else None)
+    # both routings: half of the cells scatter-dominated
+    wl.sigma_s[::3] *= 5.0
+    st, ref = _run_both(wl, wl.nsteps)
+    _compare(st, ref, TOL64)
+
+
+def test_without_velocity_estimate():
+    wl = W.small_case(3, (10, 9, 8), ("ls", 4), seed=7, nsteps=3, vscale=0.1)
+    st, ref = _run_both(wl, 3, estimate_v=False)
+    _compare(st, ref, TOL64)
+
+
+def test_transport_increment_matches_oracle():
+    import oracle
+    wl = W.small_case(3, (14, 11, 9), ("ls", 6), seed=3, vscale=0.08, kappa_a=1.0, kappa_s=40.0,
+                      bc=((W.BC_FIXED, W.BC_VACUUM), (0, 0), (W.BC_COPY, W.BC_FIXED)),
+                      ghost_seed=8)
+    s = _solver(wl)
+    dF = s.transport().double().cpu().numpy()
+    s.close()
+    prob = oracle.Problem(wl)
+    I0 = wl.init(prob.mu)
+    E, F, Pr = oracle.moments(prob, I0)
+    ref = oracle.transport(prob, wl.dt, I0, E / (4 * np.pi), wl.v, wl.sigma_a, wl.sigma_s)
+    assert _nerr(dF, ref) <= TOL64
+
+
+def test_unfused_equals_fused():
+    wl = W.small_case(3, (16, 12, 10), ("ls", 6), seed=9, vscale=0.05, kappa_s=4.0)
+    a = _solver(wl)
+    b = _solver(wl)
+    for _ in range(3):
+        a.step(1)
+        dF = b.transport()
+        b.source(dF)
+    sa, sb = a.state(), b.state()
+    a.close()
+    b.close()
+    for k in ("I", "T", "E", "F", "P", "dEgas", "dMom"):
+        assert _nerr(sb[k], sa[k]) <= 1e-13, k
+
+
+def test_exact_shift_courant_one():
+    mu = np.array([[1.0, 0, 0], [-1.0, 0, 0], [0, 1.0, 0], [0, -1.0, 0], [0, 0, 1.0],
+                   [0, 0, -1.0]])
+    w = np.array([0.25, 0.25, 0.125, 0.125, 0.125, 0.125])
+    wl = W.small_case(3, (16, 8, 6), ("table", mu, w), courant=1.0, kappa_a=0.0, kappa_s=0.0,
+                      vscale=0.0)
+    wl.dx = (1.0, 1.0, 1.0)
+    rng = np.random.default_rng(3)
+    n = wl.n
+    base = (rng.uniform(size=(6, n[2], n[1], n[0])) > 0.6).astype(float)
+    s = _solver(wl, mu=mu, w=w, I0=base.reshape(6, -1), T0=np.ones(wl.ncell))
+    s.step(1, dt=1.0)
+    got = s.state()["I"].reshape(base.shape)
+    for m in range(6):
+        d = int(np.argmax(np.abs(mu[m])))
+        exp = np.roll(base[m], int(np.sign(mu[m, d])), axis=2 - d)
+        assert np.array_equal(got[m], exp), m
+    s.step(47, dt=1.0)                       # lcm(16, 8, 6) = 48 steps in total
+    assert np.array_equal(s.state()["I"].reshape(base.shape), base)
+    s.close()
+
+
+def test_equilibrium_preserved():
+    wl = W.small_case(3, (20, 12, 9), ("ls", 8), seed=1, vscale=0.0, C=5.0)
+    wl.T[:] = 1.7
+    wl.rho[:] = 0.9
+    wl.sigma_a[:] = 3.0
+    wl.sigma_s[:] = 1.0
+    s = _solver(wl)
+    I0 = s.state()["I"]
+    s.step(20)
+    st = s.state()
+    s.close()
+    assert np.abs(st["I"] - I0).max() <= 16 * np.finfo(float).eps * I0.max()
+    assert np.abs(st["T"] - 1.7).max() <= 16 * np.finfo(float).eps * 1.7
+
+
+def test_newton_failure_is_reported():
+    from paper_1403_6126_amd import rt
+    wl = W.small_case(3, (8, 8, 8), ("ls", 4), seed=2, kappa_a=1e4, kappa_s=0.0)
+    wl.T[:] = 1e-3          # far from the radiation temperature: needs many iterations
+    s = _solver(wl, newton_maxit=1, I0=np.ones((24, wl.ncell)))
+    s.step(1)
+    assert s.status() == rt.RT_ENOCONV
+    assert s.status() == rt.RT_OK          # cleared after being reported
+    s.close()
+
+
+def test_cfl_violation_is_rejected():
+    from paper_1403_6126_amd import rt
+    wl = W.small_case(3, (8, 8, 8), ("ls", 4), seed=2)
+    s = _solver(wl)
+    with pytest.raises(rt.RTError) as ei:
+        s.step(1, dt=1.0)
+    assert ei.value.status == rt.RT_ECFL
+    s.close()
+
+
+@pytest.mark.parametrize("ndim,shape,quad", [(1, (512,), ("gl", 16)), (3, (18, 14, 11), ("ls", 8))])
+def test_mixed_precision_within_1e5(ndim, shape, quad):
+    import oracle
+    if ndim == 1:
+        wl = W.config1(nsteps=100)
+    else:
+        wl = W.small_case(ndim, shape, quad, seed=41, nsteps=20, kappa_a=1.0, kappa_s=3.0,
+                          vscale=0.02)
+    s = _solver(wl, precision="mixed")
+    s.step(wl.nsteps)
+    st = s.state()
+    assert s.status() == 0
+    s.close()
+    ref = oracle.run(wl, nsteps=wl.nsteps)
+    errs = {k: _nerr(st[k], v) for k, v in dict(E=ref.E, F=ref.F, T=ref.T).items()}
+    tref = ref.totals()
+    etot = lambda t: t[0] + t[1]
+    errs["energy"] = abs(etot(st["totals"]) - etot(tref)) / abs(etot(tref))
+    print("mixed errors", errs, flush=True)
+    assert max(errs.values()) <= 1e-5, errs
