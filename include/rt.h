@@ -130,7 +130,9 @@ typedef struct rt_out { /* device arrays; any pointer may be NULL */
 int rt_quadrature(int kind, int order, double *mu, double *w, int cap);
 
 /* Creates a context on the current HIP device: validates the grid, the angle
- * set (sum w = 1 within 1e-12, |n| = 1 within 1e-12) and the parameters,
+ * set (sum w = 1 within 1e-12; |n| = 1 within 1e-12 on 2D/3D grids, |n| <= 1
+ * on 1D slabs, whose directions may be azimuthal averages (mu, 0, 0)) and the
+ * parameters,
  * copies the angle table to the device and allocates the library-owned
  * scratch (double-buffered moment fields, per-block partial totals, a
  * status word).  *out receives the context, or NULL on failure. */

@@ -247,7 +247,9 @@ int rt_create(const rt_grid *g, const rt_angles *an, const rt_params *p, rt_ctx 
   for (int m = 0; m < an->n; ++m) {
     const double *n = an->mu + 3 * m;
     const double nn = std::sqrt(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
-    if (!(std::fabs(nn - 1.0) <= 1e-12) || !(an->w[m] > 0.0)) return RT_EBADQUAD;
+    // 1D slabs may use azimuthally averaged directions (mu, 0, 0), |n| <= 1
+    const bool norm_ok = g->ndim == 1 ? nn <= 1.0 + 1e-12 : std::fabs(nn - 1.0) <= 1e-12;
+    if (!norm_ok || !(an->w[m] > 0.0)) return RT_EBADQUAD;
     wsum += an->w[m];
   }
   if (!(std::fabs(wsum - 1.0) <= 1e-12)) return RT_EBADQUAD;
