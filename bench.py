@@ -57,7 +57,7 @@ def run_gpu(wl, precision: str, steps: int, warmup: int):
 
     mu, w = quadrature_for(wl.quad)
     T = torch.as_tensor(wl.T).cuda()
-    I0 = W.equilibrium_intensity(T, len(w), xp=torch)
+    I0 = W.equilibrium_intensity(T, len(w), xp=torch)  # (nang, ncell), expanded view
     s = Solver(wl, precision=precision, mu=mu, w=w, I0=I0)
     del I0
     info = rt.rt_get_info(s.ctx)
@@ -123,6 +123,11 @@ def main():
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=12.0)
+    ap.add_argument("--only", choices=["fp64", "mixed"], default=None,
+                    help="profiling: run one precision only and print its timing")
+    ap.add_argument("--copy-probe", type=float, default=0.0,
+                    help="profiling: time a plain device-to-device copy of this many GiB "
+                         "(counter calibration) and exit")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); multi-GPU runs "
@@ -135,10 +140,25 @@ def main():
 
     assert torch.cuda.is_available(), "no GPU visible"
     torch.cuda.set_device(0)
+    if args.copy_probe > 0:
+        n = int(args.copy_probe * (1 << 30)) // 8
+        src = torch.ones(n, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(args.steps):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes_each_way": 8 * n, "launches": args.steps}))
+        return
     wl = W.config2(nper=args.nper)
     wname = f"box3d-{args.nper}^3-S8"
     print(f"bench: {wname} fp64 warmup={args.warmup} steps={args.steps}", file=sys.stderr,
           flush=True)
+    if args.only:
+        r = run_gpu(wl, args.only, args.steps, args.warmup)
+        print(json.dumps({"precision": args.only, "kernel_ms": r["kernel_ms"],
+                          "value": r["value"], "achieved_gbs": r["achieved_gbs"],
+                          "bytes_per_launch": r["bytes_per_launch"]}), flush=True)
+        return
     r64 = run_gpu(wl, "fp64", args.steps, args.warmup)
     print(f"bench: fp64 {r64['value']:.4g} cell-angle/s, kernel {r64['kernel_ms']:.3f} ms",
           file=sys.stderr, flush=True)

@@ -26,9 +26,9 @@
  *   - per-cell scalars: [ncell] doubles;
  *   - vectors (v, F_r, dMom): [3][ncell] doubles (component-major);
  *   - pressure tensor P_r: [6][ncell] doubles, order xx, yy, zz, xy, xz, yz;
- *   - intensities I and transport increments dF: [nang][ncell] in the
+ *   - intensities I and transport increments dF: [ncell][nang] in the
  *     storage type of the context (double for RT_FP64, float for
- *     RT_FP32_MIXED), angle-major.
+ *     RT_FP32_MIXED): the angles of a cell are contiguous.
  *
  * Calls are asynchronous on the given stream (a hipStream_t passed as a
  * void pointer; NULL is the default stream).  A context is not thread safe:
@@ -132,17 +132,17 @@ int rt_quadrature(int kind, int order, double *mu, double *w, int cap);
 /* Creates a context on the current HIP device: validates the grid, the angle
  * set (sum w = 1 within 1e-12; |n| = 1 within 1e-12 on 2D/3D grids, |n| <= 1
  * on 1D slabs, whose directions may be azimuthal averages (mu, 0, 0)) and the
- * parameters,
- * copies the angle table to the device and allocates the library-owned
- * scratch (double-buffered moment fields, per-block partial totals, a
- * status word).  *out receives the context, or NULL on failure. */
+ * parameters, copies the angle table to the device and allocates the
+ * library-owned scratch: double-buffered per-cell moment fields (E, F, P and
+ * 3 v J), the per-call interface table (alpha, flow speed), per-block partial
+ * totals and a status word.  *out receives the context, or NULL on failure. */
 int rt_create(const rt_grid *g, const rt_angles *a, const rt_params *p, rt_ctx **out);
 
 /* Frees the context and its scratch (synchronises the device first). */
 int rt_destroy(rt_ctx *ctx);
 
-/* Binds two caller-owned device buffers of nang*ncell elements of the
- * storage type; I_a holds the current state.  The library ping-pongs
+/* Binds two caller-owned device buffers of ncell*nang elements of the
+ * storage type (layout [ncell][nang]); I_a holds the current state.  The library ping-pongs
  * between them; rt_current_intensity tells which one is current. */
 int rt_bind_intensity(rt_ctx *ctx, void *I_a, void *I_b);
 int rt_current_intensity(rt_ctx *ctx, void **I_cur);
@@ -156,7 +156,7 @@ int rt_set_fixed_bc(rt_ctx *ctx, int axis, int side, const double *I_ghost);
  * Pr, and into the context's moment fields used by the next step. */
 int rt_moments(rt_ctx *ctx, rt_out *out, void *stream);
 
-/* Step 2 alone: writes the transport increment dF [nang][ncell] (storage
+/* Step 2 alone: writes the transport increment dF [ncell][nang] (storage
  * type) of the current intensities for time step dt (Section 4.2). */
 int rt_transport(rt_ctx *ctx, double dt, const rt_fields *f, void *dF, void *stream);
 

@@ -9,7 +9,7 @@
 #include <vector>
 
 #include "rt.h"
-#include "rt_kernels.hpp"
+#include "rt_step_kernels.hpp"
 
 using namespace rtk;
 
@@ -25,8 +25,10 @@ struct rt_ctx {
   double *d_mu = nullptr, *d_w = nullptr, *d_ghost = nullptr;
   void *I[2] = {nullptr, nullptr};
   int cur = 0;
-  double *mom[2] = {nullptr, nullptr};
+  double *mom[2] = {nullptr, nullptr};  // [13][ncell]: E, F, P, 3vJ
   int mom_cur = 0;
+  double *faces = nullptr;              // [3][3][ncell] interface table of the call
+  int slots = 8;                        // lanes per cell of the step kernels
   bool mom_valid = false;
   double *partials = nullptr;
   double *acc = nullptr;
@@ -45,7 +47,7 @@ bool hip_ok(hipError_t e) { return e == hipSuccess; }
 
 int storage_bytes(const rt_ctx *c) { return c->p.precision == RT_FP32_MIXED ? 4 : 8; }
 
-void fill_args(const rt_ctx *c, double dt, const rt_fields *f, StepArgs &a) {
+void fill_args(const rt_ctx *c, double dt, const rt_fields *f, Step2Args &a) {
   std::memset(&a, 0, sizeof(a));
   a.ndim = c->g.ndim;
   for (int d = 0; d < 3; ++d) {
@@ -73,6 +75,7 @@ void fill_args(const rt_ctx *c, double dt, const rt_fields *f, StepArgs &a) {
   a.mu = c->d_mu;
   a.w = c->d_w;
   a.ghost = c->d_ghost;
+  a.faces = c->faces;
   if (f) {
     a.sa = f->sigma_a;
     a.ss = f->sigma_s;
@@ -94,63 +97,115 @@ int check_dt(const rt_ctx *c, double dt) {
   return RT_OK;
 }
 
-template <typename S>
-void launch_moments(const rt_ctx *c, const StepArgs &a, hipStream_t s) {
-  hipLaunchKernelGGL(k_moments<S>, dim3((unsigned)c->nblocks), dim3(kBlock), 0, s, a);
+// Lanes per cell: a power of two that gives every lane at most 10 angles
+// (16 up to 1024 angles).
+int pick_slots(int nang) {
+  if (nang <= 80) return 8;
+  if (nang <= 160) return 16;
+  if (nang <= 320) return 32;
+  return 64;
 }
 
-template <typename S, typename A, bool FUSED>
-void launch_step_t(const rt_ctx *c, const StepArgs &a, hipStream_t s) {
-  if (c->all_periodic)
-    hipLaunchKernelGGL((k_step<S, A, true, FUSED>), dim3((unsigned)c->nblocks), dim3(kBlock), 0,
-                       s, a);
+long long blocks_for(const rt_ctx *c) { return (c->ncell + (kBlock / c->slots) - 1) / (kBlock / c->slots); }
+
+template <typename S, typename A, int SL, int KM>
+void launch_step_s(const rt_ctx *c, const Step2Args &a, bool fused, hipStream_t s) {
+  dim3 g((unsigned)blocks_for(c)), b(kBlock);
+  if (c->all_periodic) {
+    if (fused)
+      hipLaunchKernelGGL((k_step2<S, A, SL, KM, true, true>), g, b, 0, s, a);
+    else
+      hipLaunchKernelGGL((k_step2<S, A, SL, KM, true, false>), g, b, 0, s, a);
+  } else {
+    if (fused)
+      hipLaunchKernelGGL((k_step2<S, A, SL, KM, false, true>), g, b, 0, s, a);
+    else
+      hipLaunchKernelGGL((k_step2<S, A, SL, KM, false, false>), g, b, 0, s, a);
+  }
+}
+
+template <typename S, typename A>
+void launch_step_p(const rt_ctx *c, const Step2Args &a, bool fused, hipStream_t s) {
+  switch (c->slots) {
+    case 8: launch_step_s<S, A, 8, 10>(c, a, fused, s); break;
+    case 16: launch_step_s<S, A, 16, 10>(c, a, fused, s); break;
+    case 32: launch_step_s<S, A, 32, 10>(c, a, fused, s); break;
+    default: launch_step_s<S, A, 64, 16>(c, a, fused, s); break;
+  }
+}
+
+void launch_step(const rt_ctx *c, const Step2Args &a, bool fused, hipStream_t s) {
+  if (c->p.precision == RT_FP32_MIXED)
+    launch_step_p<float, float>(c, a, fused, s);
   else
-    hipLaunchKernelGGL((k_step<S, A, false, FUSED>), dim3((unsigned)c->nblocks), dim3(kBlock), 0,
-                       s, a);
+    launch_step_p<double, double>(c, a, fused, s);
 }
 
-void launch_step(const rt_ctx *c, const StepArgs &a, bool fused, hipStream_t s) {
-  if (c->p.precision == RT_FP32_MIXED) {
-    if (fused)
-      launch_step_t<float, float, true>(c, a, s);
-    else
-      launch_step_t<float, float, false>(c, a, s);
-  } else {
-    if (fused)
-      launch_step_t<double, double, true>(c, a, s);
-    else
-      launch_step_t<double, double, false>(c, a, s);
+template <typename S, typename A, int SL, int KM>
+void launch_transport_s(const rt_ctx *c, const Step2Args &a, hipStream_t s) {
+  dim3 g((unsigned)blocks_for(c)), b(kBlock);
+  if (c->all_periodic)
+    hipLaunchKernelGGL((k_transport2<S, A, SL, KM, true>), g, b, 0, s, a);
+  else
+    hipLaunchKernelGGL((k_transport2<S, A, SL, KM, false>), g, b, 0, s, a);
+}
+
+template <typename S, typename A>
+void launch_transport_p(const rt_ctx *c, const Step2Args &a, hipStream_t s) {
+  switch (c->slots) {
+    case 8: launch_transport_s<S, A, 8, 10>(c, a, s); break;
+    case 16: launch_transport_s<S, A, 16, 10>(c, a, s); break;
+    case 32: launch_transport_s<S, A, 32, 10>(c, a, s); break;
+    default: launch_transport_s<S, A, 64, 16>(c, a, s); break;
   }
 }
 
-void launch_transport(const rt_ctx *c, const StepArgs &a, hipStream_t s) {
-  dim3 grid((unsigned)c->nblocks), blk(kBlock);
-  if (c->p.precision == RT_FP32_MIXED) {
-    if (c->all_periodic)
-      hipLaunchKernelGGL((k_transport<float, float, true>), grid, blk, 0, s, a);
-    else
-      hipLaunchKernelGGL((k_transport<float, float, false>), grid, blk, 0, s, a);
-  } else {
-    if (c->all_periodic)
-      hipLaunchKernelGGL((k_transport<double, double, true>), grid, blk, 0, s, a);
-    else
-      hipLaunchKernelGGL((k_transport<double, double, false>), grid, blk, 0, s, a);
+void launch_transport(const rt_ctx *c, const Step2Args &a, hipStream_t s) {
+  if (c->p.precision == RT_FP32_MIXED)
+    launch_transport_p<float, float>(c, a, s);
+  else
+    launch_transport_p<double, double>(c, a, s);
+}
+
+template <typename S>
+void launch_moments_p(const rt_ctx *c, const Step2Args &a, hipStream_t s) {
+  dim3 g((unsigned)blocks_for(c)), b(kBlock);
+  switch (c->slots) {
+    case 8: hipLaunchKernelGGL((k_moments2<S, 8>), g, b, 0, s, a); break;
+    case 16: hipLaunchKernelGGL((k_moments2<S, 16>), g, b, 0, s, a); break;
+    case 32: hipLaunchKernelGGL((k_moments2<S, 32>), g, b, 0, s, a); break;
+    default: hipLaunchKernelGGL((k_moments2<S, 64>), g, b, 0, s, a); break;
   }
+}
+
+void launch_moments(const rt_ctx *c, const Step2Args &a, hipStream_t s) {
+  if (c->p.precision == RT_FP32_MIXED)
+    launch_moments_p<float>(c, a, s);
+  else
+    launch_moments_p<double>(c, a, s);
 }
 
 int ensure_moments(rt_ctx *c, hipStream_t s) {
   if (c->mom_valid) return RT_OK;
-  StepArgs a;
+  Step2Args a;
   fill_args(c, 1.0, nullptr, a);
   a.I_in = c->I[c->cur];
   a.mom_out = c->mom[c->mom_cur];
-  if (c->p.precision == RT_FP32_MIXED)
-    launch_moments<float>(c, a, s);
-  else
-    launch_moments<double>(c, a, s);
+  launch_moments(c, a, s);
   if (!hip_ok(hipGetLastError())) return RT_EDEVICE;
   c->mom_valid = true;
   return RT_OK;
+}
+
+// Per-call tables: interface alpha / flow speed / IV Courant factor for this
+// dt and fields, and 3 v J of the current moments.
+int prepare_call(rt_ctx *c, double dt, const rt_fields *f, hipStream_t s) {
+  Step2Args a;
+  fill_args(c, dt, f, a);
+  const long long nb = (c->ncell + kBlock - 1) / kBlock;
+  hipLaunchKernelGGL(k_faces, dim3((unsigned)nb), dim3(kBlock), 0, s, a, c->faces,
+                     c->mom[c->mom_cur]);
+  return hip_ok(hipGetLastError()) ? RT_OK : RT_EDEVICE;
 }
 
 hipEvent_t take_event(rt_ctx *c) {
@@ -167,7 +222,7 @@ hipEvent_t take_event(rt_ctx *c) {
 // One step (fused or from a given dF); swaps the current buffers.
 int one_step(rt_ctx *c, double dt, const rt_fields *f, const void *dF, bool fused, rt_out *o,
              bool first, bool last, hipStream_t s) {
-  StepArgs a;
+  Step2Args a;
   fill_args(c, dt, f, a);
   a.I_in = c->I[c->cur];
   a.I_out = c->I[1 - c->cur];
@@ -196,7 +251,7 @@ int one_step(rt_ctx *c, double dt, const rt_fields *f, const void *dF, bool fuse
     hipEventRecord(e1, s);
     c->pending.emplace_back(e0, e1);
   }
-  hipLaunchKernelGGL(k_totals, dim3(1), dim3(kBlock), 0, s, c->partials, (int)c->nblocks,
+  hipLaunchKernelGGL(k_totals, dim3(1), dim3(kBlock), 0, s, c->partials, (int)blocks_for(c),
                      c->acc, first ? 1 : 0, (last && o) ? o->totals : nullptr);
   if (!hip_ok(hipGetLastError())) return RT_EDEVICE;
   c->cur = 1 - c->cur;
@@ -282,12 +337,14 @@ int rt_create(const rt_grid *g, const rt_angles *an, const rt_params *p, rt_ctx 
     }
     if (s > c->cfl_sum) c->cfl_sum = s;
   }
-  c->nblocks = (nc + kBlock - 1) / kBlock;
+  c->slots = pick_slots(N);
+  c->nblocks = blocks_for(c);
   bool ok = hip_ok(hipMalloc(&c->d_mu, sizeof(double) * 3 * N)) &&
             hip_ok(hipMalloc(&c->d_w, sizeof(double) * N)) &&
             hip_ok(hipMalloc(&c->d_ghost, sizeof(double) * 6 * N)) &&
-            hip_ok(hipMalloc(&c->mom[0], sizeof(double) * kNmom * nc)) &&
-            hip_ok(hipMalloc(&c->mom[1], sizeof(double) * kNmom * nc)) &&
+            hip_ok(hipMalloc(&c->mom[0], sizeof(double) * kNmomX * nc)) &&
+            hip_ok(hipMalloc(&c->mom[1], sizeof(double) * kNmomX * nc)) &&
+            hip_ok(hipMalloc(&c->faces, sizeof(double) * 9 * nc)) &&
             hip_ok(hipMalloc(&c->partials, sizeof(double) * kNtot * c->nblocks)) &&
             hip_ok(hipMalloc(&c->acc, sizeof(double) * kNtot)) &&
             hip_ok(hipMalloc(&c->status, sizeof(int)));
@@ -315,6 +372,7 @@ int rt_destroy(rt_ctx *c) {
   hipFree(c->d_ghost);
   hipFree(c->mom[0]);
   hipFree(c->mom[1]);
+  hipFree(c->faces);
   hipFree(c->partials);
   hipFree(c->acc);
   hipFree(c->status);
@@ -357,7 +415,7 @@ int rt_moments(rt_ctx *c, rt_out *o, void *stream) {
   if (!c) return RT_EINVAL;
   if (!c->I[0]) return RT_ESTATE;
   hipStream_t s = (hipStream_t)stream;
-  StepArgs a;
+  Step2Args a;
   fill_args(c, 1.0, nullptr, a);
   a.I_in = c->I[c->cur];
   a.mom_out = c->mom[c->mom_cur];
@@ -366,10 +424,7 @@ int rt_moments(rt_ctx *c, rt_out *o, void *stream) {
     a.oF = o->Fr;
     a.oP = o->Pr;
   }
-  if (c->p.precision == RT_FP32_MIXED)
-    launch_moments<float>(c, a, s);
-  else
-    launch_moments<double>(c, a, s);
+  launch_moments(c, a, s);
   if (!hip_ok(hipGetLastError())) return RT_EDEVICE;
   c->mom_valid = true;
   return RT_OK;
@@ -383,7 +438,9 @@ int rt_transport(rt_ctx *c, double dt, const rt_fields *f, void *dF, void *strea
   hipStream_t s = (hipStream_t)stream;
   st = ensure_moments(c, s);
   if (st != RT_OK) return st;
-  StepArgs a;
+  st = prepare_call(c, dt, f, s);
+  if (st != RT_OK) return st;
+  Step2Args a;
   fill_args(c, dt, f, a);
   a.I_in = c->I[c->cur];
   a.mom_in = c->mom[c->mom_cur];
@@ -400,6 +457,8 @@ int rt_source_implicit(rt_ctx *c, double dt, const rt_fields *f, const void *dF,
   hipStream_t s = (hipStream_t)stream;
   int st = ensure_moments(c, s);
   if (st != RT_OK) return st;
+  st = prepare_call(c, dt, f, s);
+  if (st != RT_OK) return st;
   return one_step(c, dt, f, dF, false, o, true, true, s);
 }
 
@@ -410,6 +469,8 @@ int rt_step(rt_ctx *c, double dt, int nsteps, const rt_fields *f, rt_out *o, voi
   if (st != RT_OK) return st;
   hipStream_t s = (hipStream_t)stream;
   st = ensure_moments(c, s);
+  if (st != RT_OK) return st;
+  st = prepare_call(c, dt, f, s);
   if (st != RT_OK) return st;
   for (int k = 0; k < nsteps; ++k) {
     st = one_step(c, dt, f, nullptr, true, o, k == 0, k == nsteps - 1, s);
@@ -461,7 +522,7 @@ int rt_get_info(rt_ctx *c, rt_info *info) {
   info->ncell = c->ncell;
   info->storage_bytes = storage_bytes(c);
   info->block_threads = kBlock;
-  info->grid_blocks = c->nblocks;
+  info->grid_blocks = blocks_for(c);
   return RT_OK;
 }
 

@@ -1,0 +1,116 @@
+// Shared device helpers of the radiative-transfer kernels: constants, the
+// reduced transport speed factor alpha (Section 4.2), deterministic wave and
+// block reductions, and the reduction of per-block partial totals.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace rtk {
+
+constexpr int kBlock = 256;
+constexpr int kNtot = 12;
+constexpr int kNmom = 10;  // E, F(3), P(6)
+constexpr double kFourPi = 12.566370614359172953850573533118;
+constexpr double kPi = 3.1415926535897932384626433832795;
+
+enum BcKind : int { kPeriodic = 0, kFixed = 1, kCopy = 2, kVacuum = 3 };
+
+
+
+// ----------------------------------------------------------------- helpers
+// van Leer harmonic-mean slope of the one-sided differences (zero at
+// extrema), and the upwind interface value of the piecewise-linear
+// reconstruction at Courant number nu, with h = (1 - nu)/2.
+template <typename A>
+__device__ __forceinline__ A van_leer(A a, A b) {
+  const A ab = a * b;
+  return ab > A(0) ? (A(2) * ab) / (a + b) : A(0);
+}
+template <typename A>
+__device__ __forceinline__ A upwind_face(A up2, A up1, A dn1, A h) {
+  return up1 + h * van_leer(up1 - up2, dn1 - up1);
+}
+
+// alpha = sqrt((1 - exp(-tau))/tau), tau = (10 dl sigma)^2, alpha(0) = 1
+__device__ __forceinline__ double alpha_of(double sigma, double dl10) {
+  const double s = dl10 * sigma;
+  const double tau = s * s;
+  return tau > 0.0 ? sqrt(-expm1(-tau) / tau) : 1.0;
+}
+
+__device__ __forceinline__ double wave_sum(double x) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
+  return x;
+}
+__device__ __forceinline__ double wave_min(double x) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) x = fmin(x, __shfl_xor(x, o, 64));
+  return x;
+}
+__device__ __forceinline__ double wave_max(double x) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) x = fmax(x, __shfl_xor(x, o, 64));
+  return x;
+}
+
+// Deterministic per-block reduction of the totals vector into partials.
+__device__ __forceinline__ void block_totals(double (&t)[kNtot], double *partials) {
+  __shared__ double red[kBlock / 64][kNtot];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+  for (int k = 0; k < kNtot; ++k) {
+    double x = t[k];
+    x = (k == 10) ? wave_min(x) : (k == 11) ? wave_max(x) : wave_sum(x);
+    if (lane == 0) red[wid][k] = x;
+  }
+  __syncthreads();
+  if (threadIdx.x < kNtot) {
+    const int k = threadIdx.x;
+    double x = red[0][k];
+    for (int q = 1; q < kBlock / 64; ++q)
+      x = (k == 10) ? fmin(x, red[q][k]) : (k == 11) ? fmax(x, red[q][k]) : x + red[q][k];
+    partials[(size_t)blockIdx.x * kNtot + k] = x;
+  }
+}
+
+// Deterministic reduction of the per-block partial totals.  acc holds the
+// running sums over the steps of a call of entries 2..6 (reset when
+// reset != 0); out receives the totals when non-null.
+__global__ __launch_bounds__(kBlock) void k_totals(const double *partials, int nblocks,
+                                                   double *acc, int reset, double *out) {
+  __shared__ double red[kBlock];
+  __shared__ double res[kNtot];
+  for (int k = 0; k < kNtot; ++k) {
+    double x = (k == 10) ? 1.0e300 : (k == 11) ? 0.0 : 0.0;
+    for (int b = threadIdx.x; b < nblocks; b += kBlock) {
+      const double y = partials[(size_t)b * kNtot + k];
+      x = (k == 10) ? fmin(x, y) : (k == 11) ? fmax(x, y) : x + y;
+    }
+    red[threadIdx.x] = x;
+    __syncthreads();
+    for (int s = kBlock / 2; s > 0; s >>= 1) {
+      if (threadIdx.x < s) {
+        const double y = red[threadIdx.x + s];
+        red[threadIdx.x] = (k == 10)   ? fmin(red[threadIdx.x], y)
+                           : (k == 11) ? fmax(red[threadIdx.x], y)
+                                       : red[threadIdx.x] + y;
+      }
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) res[k] = red[0];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    for (int k = 2; k <= 6; ++k) {
+      acc[k] = (reset ? 0.0 : acc[k]) + res[k];
+      res[k] = acc[k];
+    }
+    acc[11] = reset ? res[11] : fmax(acc[11], res[11]);
+    res[11] = acc[11];
+    if (out)
+      for (int k = 0; k < kNtot; ++k) out[k] = res[k];
+  }
+}
+
+}  // namespace rtk

@@ -74,7 +74,7 @@ def equilibrium_intensity(T: np.ndarray, nang: int, xp=np) -> np.ndarray:
     base = T ** 4 / FOUR_PI
     if xp is np:
         return np.broadcast_to(base, (nang, base.shape[0])).copy()
-    return base.unsqueeze(0).expand(nang, base.shape[0]).contiguous()
+    return base.unsqueeze(0).expand(nang, base.shape[0])
 
 
 def moment_intensity(mu, E, F, xp=np):
