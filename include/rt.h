@@ -26,9 +26,9 @@
  *   - per-cell scalars: [ncell] doubles;
  *   - vectors (v, F_r, dMom): [3][ncell] doubles (component-major);
  *   - pressure tensor P_r: [6][ncell] doubles, order xx, yy, zz, xy, xz, yz;
- *   - intensities I and transport increments dF: [ncell][nang] in the
+ *   - intensities I and transport increments dF: [nang][ncell] in the
  *     storage type of the context (double for RT_FP64, float for
- *     RT_FP32_MIXED): the angles of a cell are contiguous.
+ *     RT_FP32_MIXED): one contiguous plane of cells per angle.
  *
  * Calls are asynchronous on the given stream (a hipStream_t passed as a
  * void pointer; NULL is the default stream).  A context is not thread safe:
@@ -141,8 +141,8 @@ int rt_create(const rt_grid *g, const rt_angles *a, const rt_params *p, rt_ctx *
 /* Frees the context and its scratch (synchronises the device first). */
 int rt_destroy(rt_ctx *ctx);
 
-/* Binds two caller-owned device buffers of ncell*nang elements of the
- * storage type (layout [ncell][nang]); I_a holds the current state.  The library ping-pongs
+/* Binds two caller-owned device buffers of nang*ncell elements of the
+ * storage type (layout [nang][ncell]); I_a holds the current state.  The library ping-pongs
  * between them; rt_current_intensity tells which one is current. */
 int rt_bind_intensity(rt_ctx *ctx, void *I_a, void *I_b);
 int rt_current_intensity(rt_ctx *ctx, void **I_cur);
@@ -156,7 +156,7 @@ int rt_set_fixed_bc(rt_ctx *ctx, int axis, int side, const double *I_ghost);
  * Pr, and into the context's moment fields used by the next step. */
 int rt_moments(rt_ctx *ctx, rt_out *out, void *stream);
 
-/* Step 2 alone: writes the transport increment dF [ncell][nang] (storage
+/* Step 2 alone: writes the transport increment dF [nang][ncell] (storage
  * type) of the current intensities for time step dt (Section 4.2). */
 int rt_transport(rt_ctx *ctx, double dt, const rt_fields *f, void *dF, void *stream);
 

@@ -9,7 +9,8 @@
 #include <vector>
 
 #include "rt.h"
-#include "rt_step_kernels.hpp"
+#include "rt_fallback.hpp"
+#include "rt_step3.hpp"
 
 using namespace rtk;
 
@@ -28,7 +29,7 @@ struct rt_ctx {
   double *mom[2] = {nullptr, nullptr};  // [13][ncell]: E, F, P, 3vJ
   int mom_cur = 0;
   double *faces = nullptr;              // [3][3][ncell] interface table of the call
-  int slots = 8;                        // lanes per cell of the step kernels
+  int waves = 0;                        // waves per block of k_step3 (0: thread-per-cell kernel)
   bool mom_valid = false;
   double *partials = nullptr;
   double *acc = nullptr;
@@ -47,7 +48,7 @@ bool hip_ok(hipError_t e) { return e == hipSuccess; }
 
 int storage_bytes(const rt_ctx *c) { return c->p.precision == RT_FP32_MIXED ? 4 : 8; }
 
-void fill_args(const rt_ctx *c, double dt, const rt_fields *f, Step2Args &a) {
+void fill_args(const rt_ctx *c, double dt, const rt_fields *f, StepArgs &a) {
   std::memset(&a, 0, sizeof(a));
   a.ndim = c->g.ndim;
   for (int d = 0; d < 3; ++d) {
@@ -97,97 +98,77 @@ int check_dt(const rt_ctx *c, double dt) {
   return RT_OK;
 }
 
-// Lanes per cell: a power of two that gives every lane at most 10 angles
-// (16 up to 1024 angles).
-int pick_slots(int nang) {
-  if (nang <= 80) return 8;
-  if (nang <= 160) return 16;
-  if (nang <= 320) return 32;
-  return 64;
+// Waves per block of the wave-group kernel (10 angles per wave), or 0 when
+// the angle set is larger than it handles and the thread-per-cell kernel
+// runs instead.
+constexpr int kAnglesPerWave = 10;
+int pick_waves(int nang) {
+  const int G = (nang + kAnglesPerWave - 1) / kAnglesPerWave;
+  return G <= kMaxWaves ? G : 0;
 }
 
-long long blocks_for(const rt_ctx *c) { return (c->ncell + (kBlock / c->slots) - 1) / (kBlock / c->slots); }
+long long step_blocks(const rt_ctx *c) {
+  return c->waves ? (c->ncell + 63) / 64 : (c->ncell + kBlock - 1) / kBlock;
+}
+long long cell_blocks(const rt_ctx *c) { return (c->ncell + kBlock - 1) / kBlock; }
 
-template <typename S, typename A, int SL, int KM>
-void launch_step_s(const rt_ctx *c, const Step2Args &a, bool fused, hipStream_t s) {
-  dim3 g((unsigned)blocks_for(c)), b(kBlock);
-  if (c->all_periodic) {
-    if (fused)
-      hipLaunchKernelGGL((k_step2<S, A, SL, KM, true, true>), g, b, 0, s, a);
+template <typename S, typename A, bool FUSED>
+void launch_step_t(const rt_ctx *c, const StepArgs &a, hipStream_t s) {
+  if (c->waves) {
+    dim3 g((unsigned)step_blocks(c)), b(64 * c->waves);
+    if (c->all_periodic)
+      hipLaunchKernelGGL((k_step3<S, A, kAnglesPerWave, true, FUSED>), g, b, 0, s, a);
     else
-      hipLaunchKernelGGL((k_step2<S, A, SL, KM, true, false>), g, b, 0, s, a);
+      hipLaunchKernelGGL((k_step3<S, A, kAnglesPerWave, false, FUSED>), g, b, 0, s, a);
+  } else {
+    dim3 g((unsigned)step_blocks(c)), b(kBlock);
+    if (c->all_periodic)
+      hipLaunchKernelGGL((k_step<S, A, true, FUSED>), g, b, 0, s, a);
+    else
+      hipLaunchKernelGGL((k_step<S, A, false, FUSED>), g, b, 0, s, a);
+  }
+}
+
+void launch_step(const rt_ctx *c, const StepArgs &a, bool fused, hipStream_t s) {
+  if (c->p.precision == RT_FP32_MIXED) {
+    if (fused)
+      launch_step_t<float, float, true>(c, a, s);
+    else
+      launch_step_t<float, float, false>(c, a, s);
   } else {
     if (fused)
-      hipLaunchKernelGGL((k_step2<S, A, SL, KM, false, true>), g, b, 0, s, a);
+      launch_step_t<double, double, true>(c, a, s);
     else
-      hipLaunchKernelGGL((k_step2<S, A, SL, KM, false, false>), g, b, 0, s, a);
+      launch_step_t<double, double, false>(c, a, s);
   }
 }
 
-template <typename S, typename A>
-void launch_step_p(const rt_ctx *c, const Step2Args &a, bool fused, hipStream_t s) {
-  switch (c->slots) {
-    case 8: launch_step_s<S, A, 8, 10>(c, a, fused, s); break;
-    case 16: launch_step_s<S, A, 16, 10>(c, a, fused, s); break;
-    case 32: launch_step_s<S, A, 32, 10>(c, a, fused, s); break;
-    default: launch_step_s<S, A, 64, 16>(c, a, fused, s); break;
+void launch_transport(const rt_ctx *c, const StepArgs &a, hipStream_t s) {
+  dim3 g((unsigned)cell_blocks(c)), b(kBlock);
+  if (c->p.precision == RT_FP32_MIXED) {
+    if (c->all_periodic)
+      hipLaunchKernelGGL((k_transport<float, float, true>), g, b, 0, s, a);
+    else
+      hipLaunchKernelGGL((k_transport<float, float, false>), g, b, 0, s, a);
+  } else {
+    if (c->all_periodic)
+      hipLaunchKernelGGL((k_transport<double, double, true>), g, b, 0, s, a);
+    else
+      hipLaunchKernelGGL((k_transport<double, double, false>), g, b, 0, s, a);
   }
 }
 
-void launch_step(const rt_ctx *c, const Step2Args &a, bool fused, hipStream_t s) {
+void launch_moments(const rt_ctx *c, const StepArgs &a, hipStream_t s) {
+  dim3 g((unsigned)cell_blocks(c)), b(kBlock);
   if (c->p.precision == RT_FP32_MIXED)
-    launch_step_p<float, float>(c, a, fused, s);
+    hipLaunchKernelGGL(k_moments<float>, g, b, 0, s, a);
   else
-    launch_step_p<double, double>(c, a, fused, s);
-}
-
-template <typename S, typename A, int SL, int KM>
-void launch_transport_s(const rt_ctx *c, const Step2Args &a, hipStream_t s) {
-  dim3 g((unsigned)blocks_for(c)), b(kBlock);
-  if (c->all_periodic)
-    hipLaunchKernelGGL((k_transport2<S, A, SL, KM, true>), g, b, 0, s, a);
-  else
-    hipLaunchKernelGGL((k_transport2<S, A, SL, KM, false>), g, b, 0, s, a);
-}
-
-template <typename S, typename A>
-void launch_transport_p(const rt_ctx *c, const Step2Args &a, hipStream_t s) {
-  switch (c->slots) {
-    case 8: launch_transport_s<S, A, 8, 10>(c, a, s); break;
-    case 16: launch_transport_s<S, A, 16, 10>(c, a, s); break;
-    case 32: launch_transport_s<S, A, 32, 10>(c, a, s); break;
-    default: launch_transport_s<S, A, 64, 16>(c, a, s); break;
-  }
-}
-
-void launch_transport(const rt_ctx *c, const Step2Args &a, hipStream_t s) {
-  if (c->p.precision == RT_FP32_MIXED)
-    launch_transport_p<float, float>(c, a, s);
-  else
-    launch_transport_p<double, double>(c, a, s);
-}
-
-template <typename S>
-void launch_moments_p(const rt_ctx *c, const Step2Args &a, hipStream_t s) {
-  dim3 g((unsigned)blocks_for(c)), b(kBlock);
-  switch (c->slots) {
-    case 8: hipLaunchKernelGGL((k_moments2<S, 8>), g, b, 0, s, a); break;
-    case 16: hipLaunchKernelGGL((k_moments2<S, 16>), g, b, 0, s, a); break;
-    case 32: hipLaunchKernelGGL((k_moments2<S, 32>), g, b, 0, s, a); break;
-    default: hipLaunchKernelGGL((k_moments2<S, 64>), g, b, 0, s, a); break;
-  }
-}
-
-void launch_moments(const rt_ctx *c, const Step2Args &a, hipStream_t s) {
-  if (c->p.precision == RT_FP32_MIXED)
-    launch_moments_p<float>(c, a, s);
-  else
-    launch_moments_p<double>(c, a, s);
+    hipLaunchKernelGGL(k_moments<double>, g, b, 0, s, a);
 }
 
 int ensure_moments(rt_ctx *c, hipStream_t s) {
   if (c->mom_valid) return RT_OK;
-  Step2Args a;
+  StepArgs a;
   fill_args(c, 1.0, nullptr, a);
   a.I_in = c->I[c->cur];
   a.mom_out = c->mom[c->mom_cur];
@@ -200,7 +181,7 @@ int ensure_moments(rt_ctx *c, hipStream_t s) {
 // Per-call tables: interface alpha / flow speed / IV Courant factor for this
 // dt and fields, and 3 v J of the current moments.
 int prepare_call(rt_ctx *c, double dt, const rt_fields *f, hipStream_t s) {
-  Step2Args a;
+  StepArgs a;
   fill_args(c, dt, f, a);
   const long long nb = (c->ncell + kBlock - 1) / kBlock;
   hipLaunchKernelGGL(k_faces, dim3((unsigned)nb), dim3(kBlock), 0, s, a, c->faces,
@@ -222,7 +203,7 @@ hipEvent_t take_event(rt_ctx *c) {
 // One step (fused or from a given dF); swaps the current buffers.
 int one_step(rt_ctx *c, double dt, const rt_fields *f, const void *dF, bool fused, rt_out *o,
              bool first, bool last, hipStream_t s) {
-  Step2Args a;
+  StepArgs a;
   fill_args(c, dt, f, a);
   a.I_in = c->I[c->cur];
   a.I_out = c->I[1 - c->cur];
@@ -251,7 +232,7 @@ int one_step(rt_ctx *c, double dt, const rt_fields *f, const void *dF, bool fuse
     hipEventRecord(e1, s);
     c->pending.emplace_back(e0, e1);
   }
-  hipLaunchKernelGGL(k_totals, dim3(1), dim3(kBlock), 0, s, c->partials, (int)blocks_for(c),
+  hipLaunchKernelGGL(k_totals, dim3(1), dim3(kBlock), 0, s, c->partials, (int)step_blocks(c),
                      c->acc, first ? 1 : 0, (last && o) ? o->totals : nullptr);
   if (!hip_ok(hipGetLastError())) return RT_EDEVICE;
   c->cur = 1 - c->cur;
@@ -337,8 +318,8 @@ int rt_create(const rt_grid *g, const rt_angles *an, const rt_params *p, rt_ctx 
     }
     if (s > c->cfl_sum) c->cfl_sum = s;
   }
-  c->slots = pick_slots(N);
-  c->nblocks = blocks_for(c);
+  c->waves = pick_waves(N);
+  c->nblocks = (nc + 63) / 64;  // enough partial-total rows for either kernel
   bool ok = hip_ok(hipMalloc(&c->d_mu, sizeof(double) * 3 * N)) &&
             hip_ok(hipMalloc(&c->d_w, sizeof(double) * N)) &&
             hip_ok(hipMalloc(&c->d_ghost, sizeof(double) * 6 * N)) &&
@@ -415,7 +396,7 @@ int rt_moments(rt_ctx *c, rt_out *o, void *stream) {
   if (!c) return RT_EINVAL;
   if (!c->I[0]) return RT_ESTATE;
   hipStream_t s = (hipStream_t)stream;
-  Step2Args a;
+  StepArgs a;
   fill_args(c, 1.0, nullptr, a);
   a.I_in = c->I[c->cur];
   a.mom_out = c->mom[c->mom_cur];
@@ -440,7 +421,7 @@ int rt_transport(rt_ctx *c, double dt, const rt_fields *f, void *dF, void *strea
   if (st != RT_OK) return st;
   st = prepare_call(c, dt, f, s);
   if (st != RT_OK) return st;
-  Step2Args a;
+  StepArgs a;
   fill_args(c, dt, f, a);
   a.I_in = c->I[c->cur];
   a.mom_in = c->mom[c->mom_cur];
@@ -521,8 +502,8 @@ int rt_get_info(rt_ctx *c, rt_info *info) {
   info->nang = c->nang;
   info->ncell = c->ncell;
   info->storage_bytes = storage_bytes(c);
-  info->block_threads = kBlock;
-  info->grid_blocks = blocks_for(c);
+  info->block_threads = c->waves ? 64 * c->waves : kBlock;
+  info->grid_blocks = step_blocks(c);
   return RT_OK;
 }
 

@@ -14,6 +14,37 @@ constexpr double kFourPi = 12.566370614359172953850573533118;
 constexpr double kPi = 3.1415926535897932384626433832795;
 
 enum BcKind : int { kPeriodic = 0, kFixed = 1, kCopy = 2, kVacuum = 3 };
+constexpr int kNmomX = 13;  // moments (10) + 3 v J (3)
+
+// Arguments of every step kernel (passed by value).
+struct StepArgs {
+  int ndim, n[3], ncell, nang;
+  int bc[3][2];
+  int stride[3];
+  double dt, C, invC, P, cvfac;  // cvfac = R/(gamma - 1)
+  double dt_dx[3];               // dt / dx_d
+  double dl10[3];                // 10 dx_d (transport speed factor alpha)
+  double vol, rtol;
+  int maxit, estimate_v;
+  const double *mu;      // [3][nang]
+  const double *w;       // [nang]
+  const double *ghost;   // [3][2][nang] fixed-face ghost intensities
+  const double *sa, *ss, *rho, *v;
+  double *T;
+  const double *faces;   // [3][3][ncell] alpha, hv, u of the low face of each cell
+  const double *mom_in;  // [13][ncell] E, F(3), P(6), 3vJ(3) of I^n
+  double *mom_out;       // [13][ncell] of I^{n+1}
+  double *oE, *oF, *oP;  // optional copies of the new moments
+  double *dEgas, *dMom;  // optional per-cell sums over the call
+  int accumulate;
+  double *partials;      // [grid][kNtot]
+  int *status;
+  const void *I_in;
+  void *I_out;
+  const void *dF_in;     // unfused source step: transport increment (nullable)
+  void *dF_out;          // transport-only output
+};
+
 
 
 

@@ -1,0 +1,498 @@
+// Fused step kernel with the waves of a block sharing cells (angle-major
+// layout I[m][c]).
+//
+// A block holds 64 consecutive cells (one per lane) and G = ceil(nang/KA)
+// waves; wave g owns the angles m = g*KA ... g*KA + KA - 1.  Within a wave
+// the angle is uniform, so the direction cosines, weights and the upwind
+// direction of every axis are scalars, and every intensity load reads 64
+// consecutive cells of one angle plane.  Per step:
+//   phase A  transport increment of the wave's angles (Section 4.2), one
+//            active axis at a time, from a per-call interface table (alpha,
+//            flow speed, IV Courant factor) and 3 v J carried with the
+//            moments;
+//   phase B  the absorption right-hand side r4 and the wave's partial sums of
+//            the per-cell sums of the reduced absorption and scattering
+//            systems; the per-angle values stay in registers;
+//   reduce   the partial sums across the waves (LDS, fixed order);
+//   solve    wave 0: FP64 Newton on the quartic in T' and the 2 x 2
+//            scattering system; the solution goes to the other waves via LDS;
+//   phase C  I^{n+1} of the wave's angles, written once, and the partial
+//            moments, reduced across the waves like the sums.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "rt_common.hpp"
+
+namespace rtk {
+
+constexpr int kNsum = 22;        // per-cell sums of phase B
+constexpr int kMaxWaves = 8;     // waves per block of the wave-group kernel
+constexpr int kChunk = 11;       // values reduced per LDS round
+
+// Reciprocal from the hardware estimate refined by Newton steps (two in
+// FP64; the FP32 estimate is used as is).  Within an ulp of a divide.
+__device__ __forceinline__ double fast_rcp(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  double e = __builtin_fma(-x, r, 1.0);
+  r = __builtin_fma(r, e, r);
+  e = __builtin_fma(-x, r, 1.0);
+  r = __builtin_fma(r, e, r);
+  return r;
+}
+__device__ __forceinline__ float fast_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+
+// up1 + h * vanLeer(up1 - up2, dn1 - up1), vanLeer(a, b) = 2ab/(a + b) when
+// ab > 0, else 0: the upwind interface value of the monotonic
+// piecewise-linear reconstruction at Courant factor h = (1 - nu)/2.
+template <typename A>
+__device__ __forceinline__ A vl_face(A up2, A up1, A dn1, A h) {
+  const A a = up1 - up2, b = dn1 - up1;
+  const A ab = a * b;
+  const A q = (ab + ab) * fast_rcp(a + b);
+  return up1 + h * (ab > A(0) ? q : A(0));
+}
+
+// Interface table and IV basis (once per call).  faces[(d*3 + j)*ncell + c]
+// for the face between the cell below c along axis d (wrapped; the edge cell
+// itself at a non-periodic low boundary, whose ghost copies it) and c:
+// j = 0 alpha, 1 hv = (1 - |u| dt/dx)/2, 2 u.  wv = 3 v E/(4pi) of the
+// current moments into mom[10..12].
+__global__ __launch_bounds__(kBlock) void k_faces(StepArgs p, double *faces, double *mom) {
+  const int c = blockIdx.x * kBlock + threadIdx.x;
+  if (c >= p.ncell) return;
+  const size_t N = (size_t)p.ncell;
+  const double sig_c = p.sa[c] + p.ss[c];
+  const int q[3] = {c % p.n[0], (c / p.n[0]) % p.n[1], c / (p.n[0] * p.n[1])};
+  for (int d = 0; d < p.ndim; ++d) {
+    int cl;
+    if (q[d] > 0)
+      cl = c - p.stride[d];
+    else if (p.bc[d][0] == kPeriodic)
+      cl = c + (p.n[d] - 1) * p.stride[d];
+    else
+      cl = c;
+    const double sig = 0.5 * ((p.sa[cl] + p.ss[cl]) + sig_c);
+    const double u = 0.5 * (p.v[(size_t)d * N + cl] + p.v[(size_t)d * N + c]);
+    faces[(size_t)(d * 3 + 0) * N + c] = alpha_of(sig, p.dl10[d]);
+    faces[(size_t)(d * 3 + 1) * N + c] = 0.5 * (1.0 - fabs(u) * p.dt_dx[d]);
+    faces[(size_t)(d * 3 + 2) * N + c] = u;
+  }
+  const double J = mom[c] * (1.0 / kFourPi);
+  for (int k = 0; k < 3; ++k) mom[(size_t)(10 + k) * N + c] = 3.0 * p.v[(size_t)k * N + c] * J;
+}
+
+// Stencil of one cell along one axis.
+template <typename A>
+struct Stencil {
+  int idx[4];   // cells at offsets -2, -1, +1, +2 (wrapped, or the edge cell)
+  int kind[4];  // 0 read the cell, 1 fixed table, 2 vacuum
+  A wv[4][3];   // 3 v J at those cells
+  A aL, aR, hL, hR;
+  double uL, uR;
+};
+
+template <typename A, bool PER>
+__device__ __forceinline__ void load_stencil(const StepArgs &p, int c, const int q[3], int d,
+                                             Stencil<A> &s) {
+  const int n = p.n[d];
+  const size_t N = (size_t)p.ncell;
+  const int offs[4] = {-2, -1, 1, 2};
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int k = q[d] + offs[j];
+    int kk = k, kind = 0;
+    if (k < 0 || k >= n) {
+      const int bc = PER ? kPeriodic : p.bc[d][k < 0 ? 0 : 1];
+      if (bc == kPeriodic) {
+        kk = ((k % n) + n) % n;
+      } else {
+        kk = k < 0 ? 0 : n - 1;
+        kind = bc == kFixed ? 1 : bc == kVacuum ? 2 : 0;
+      }
+    }
+    const int cj = c + (kk - q[d]) * p.stride[d];
+    s.idx[j] = cj;
+    s.kind[j] = kind;
+#pragma unroll
+    for (int t = 0; t < 3; ++t) s.wv[j][t] = A(p.mom_in[(size_t)(10 + t) * N + cj]);
+  }
+  s.aL = A(p.faces[(size_t)(d * 3 + 0) * N + c]);
+  s.hL = A(p.faces[(size_t)(d * 3 + 1) * N + c]);
+  s.uL = p.faces[(size_t)(d * 3 + 2) * N + c];
+  if (PER || q[d] + 1 < n || p.bc[d][1] == kPeriodic) {
+    const int cr = s.idx[2];
+    s.aR = A(p.faces[(size_t)(d * 3 + 0) * N + cr]);
+    s.hR = A(p.faces[(size_t)(d * 3 + 1) * N + cr]);
+    s.uR = p.faces[(size_t)(d * 3 + 2) * N + cr];
+  } else {
+    // high non-periodic boundary: the ghost copies this cell's fields
+    const double u = p.v[(size_t)d * N + c];
+    s.aR = A(alpha_of(p.sa[c] + p.ss[c], p.dl10[d]));
+    s.hR = A(0.5 * (1.0 - fabs(u) * p.dt_dx[d]));
+    s.uR = u;
+  }
+}
+
+// Intensity of angle plane Im at a stencil cell, with the ghost kinds.
+template <typename S, typename A, bool PER>
+__device__ __forceinline__ A plane_load(const StepArgs &p, const S *Im, int idx, int kind,
+                                        int side, int d, int m, A mud) {
+  if (PER || kind == 0) return A(Im[idx]);
+  if (kind == 1) return A(p.ghost[(size_t)(d * 2 + side) * p.nang + m]);
+  const bool outgoing = side == 0 ? (mud < A(0)) : (mud > A(0));
+  return outgoing ? A(Im[idx]) : A(0);
+}
+
+// Sum (or, for the last value when MINLAST, minimum) of NV values over the
+// G waves of the block, lane by lane, in a fixed order; every wave receives
+// the totals.
+template <int NV, bool MINLAST>
+__device__ __forceinline__ void waves_reduce(double (&x)[NV], double *buf, double *tot, int g,
+                                             int G, int lane) {
+  static_assert(NV <= kChunk, "chunk too large");
+#pragma unroll
+  for (int v = 0; v < NV; ++v) buf[(g * NV + v) * 64 + lane] = x[v];
+  __syncthreads();
+  for (int v = g; v < NV; v += G) {
+    double s = buf[v * 64 + lane];
+    for (int j = 1; j < G; ++j) {
+      const double y = buf[(j * NV + v) * 64 + lane];
+      s = (MINLAST && v == NV - 1) ? fmin(s, y) : s + y;
+    }
+    tot[v * 64 + lane] = s;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int v = 0; v < NV; ++v) x[v] = tot[v * 64 + lane];
+}
+
+template <typename S, typename A, int KA, bool PER, bool FUSED>
+__global__ __launch_bounds__(64 * kMaxWaves) void k_step3(StepArgs p) {
+  __shared__ double sbuf[kMaxWaves * kChunk * 64];
+  __shared__ double stot[kChunk * 64];
+  __shared__ double ssol[6 * 64];
+  const int lane = threadIdx.x & 63;
+  const int g = threadIdx.x >> 6;
+  const int G = blockDim.x >> 6;
+  const int c0 = blockIdx.x * 64 + lane;
+  const bool act = c0 < p.ncell;
+  const int c = act ? c0 : p.ncell - 1;  // idle lanes shadow the last cell
+  const int NA = p.nang;
+  const int m0 = g * KA;
+  const int KG = min(KA, NA - m0);  // angles of this wave (uniform, >= 1)
+  const size_t N = (size_t)p.ncell;
+  const S *Iin = static_cast<const S *>(p.I_in);
+  S *Iout = static_cast<S *>(p.I_out);
+  const double C = p.C, P = p.P, dt = p.dt;
+  const double sa = p.sa[c], ss = p.ss[c], rho = p.rho[c], Tn = p.T[c];
+  const double v0 = p.v[c], v1 = p.v[N + c], v2 = p.v[2 * N + c];
+
+  // ------------------------------------------------ phase A: transport
+  A Ic[KA], dF[KA];
+#pragma unroll
+  for (int k = 0; k < KA; ++k) {
+    Ic[k] = k < KG ? A(Iin[(size_t)(m0 + k) * N + c]) : A(0);
+    dF[k] = A(0);
+  }
+  if (FUSED) {
+    const int q[3] = {c % p.n[0], (c / p.n[0]) % p.n[1], c / (p.n[0] * p.n[1])};
+    const A wc0 = A(p.mom_in[10 * N + c]), wc1 = A(p.mom_in[11 * N + c]),
+            wc2 = A(p.mom_in[12 * N + c]);
+    const A AC = A(C), invC = A(p.invC);
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      if (d >= p.ndim) break;
+      Stencil<A> s;
+      load_stencil<A, PER>(p, c, q, d, s);
+      const A dtdx = A(p.dt_dx[d]);
+      const bool posR = s.uR > 0.0, posL = s.uL > 0.0;
+      const bool zeroR = s.uR == 0.0, zeroL = s.uL == 0.0;
+      constexpr int UNR = sizeof(A) == 8 ? KA : 1;
+#pragma unroll UNR
+      for (int k = 0; k < KA; ++k) {
+          const int m = m0 + k;
+          const A n0 = A(p.mu[m]), n1 = A(p.mu[NA + m]), n2 = A(p.mu[2 * NA + m]);
+          const A mud = d == 0 ? n0 : d == 1 ? n1 : n2;
+          if (k < KG && mud != A(0)) {  // uniform over the wave
+          const S *Im = Iin + (size_t)m * N;
+          A IV[4];
+#pragma unroll
+          for (int j = 0; j < 4; ++j) IV[j] = n0 * s.wv[j][0] + n1 * s.wv[j][1] + n2 * s.wv[j][2];
+          const A IVc = n0 * wc0 + n1 * wc1 + n2 * wc2;
+          const A Itc = Ic[k] - IVc * invC;
+          const A Im1 = plane_load<S, A, PER>(p, Im, s.idx[1], s.kind[1], 0, d, m, mud);
+          const A Ip1 = plane_load<S, A, PER>(p, Im, s.idx[2], s.kind[2], 1, d, m, mud);
+          const A Itm1 = Im1 - IV[1] * invC, Itp1 = Ip1 - IV[2] * invC;
+          const A h = A(0.5) * (A(1) - AC * fabs(mud) * dtdx);
+          A upR, upL;
+          if (mud > A(0)) {
+            const A Im2 = plane_load<S, A, PER>(p, Im, s.idx[0], s.kind[0], 0, d, m, mud);
+            const A Itm2 = Im2 - IV[0] * invC;
+            upR = vl_face(Itm1, Itc, Itp1, h);
+            upL = vl_face(Itm2, Itm1, Itc, h);
+          } else {
+            const A Ip2 = plane_load<S, A, PER>(p, Im, s.idx[3], s.kind[3], 1, d, m, mud);
+            const A Itp2 = Ip2 - IV[3] * invC;
+            upR = vl_face(Itp2, Itp1, Itc, h);
+            upL = vl_face(Itp1, Itc, Itm1, h);
+          }
+          const A cenR = A(0.5) * (Itc + Itp1), cenL = A(0.5) * (Itm1 + Itc);
+          const A phiR = AC * mud * (s.aR * upR + (A(1) - s.aR) * cenR);
+          const A phiL = AC * mud * (s.aL * upL + (A(1) - s.aL) * cenL);
+          A ivR, ivL;
+          {
+            const A u2 = posR ? IV[1] : IV[3], u1 = posR ? IVc : IV[2], d1 = posR ? IV[2] : IVc;
+            const A f = vl_face(u2, u1, d1, s.hR);
+            ivR = zeroR ? A(0.5) * (IVc + IV[2]) : f;
+          }
+          {
+            const A u2 = posL ? IV[0] : IV[2], u1 = posL ? IV[1] : IVc, d1 = posL ? IVc : IV[1];
+            const A f = vl_face(u2, u1, d1, s.hL);
+            ivL = zeroL ? A(0.5) * (IV[1] + IVc) : f;
+          }
+          dF[k] -= dtdx * ((phiR + mud * ivR) - (phiL + mud * ivL));
+        }
+      }
+    }
+  } else {
+    const S *dFin = static_cast<const S *>(p.dF_in);
+    if (dFin) {
+#pragma unroll
+      for (int k = 0; k < KA; ++k)
+        if (k < KG) dF[k] = A(dFin[(size_t)(m0 + k) * N + c]);
+    }
+  }
+
+  // ---------------------------------- Step 3: velocity estimate (per cell)
+  double u0 = v0, u1 = v1, u2 = v2;
+  if (p.estimate_v) {
+    const double h = 0.5 * dt * (sa + ss);
+    const double E = p.mom_in[c];
+    const double F0 = p.mom_in[N + c], F1 = p.mom_in[2 * N + c], F2 = p.mom_in[3 * N + c];
+    const double P0 = p.mom_in[4 * N + c], P1 = p.mom_in[5 * N + c], P2 = p.mom_in[6 * N + c];
+    const double base = rho + h * C * rho;
+    u0 = (rho * v0 + h * (C * rho * v0 + P * F0)) / (base + h * P * (E + P0) / C);
+    u1 = (rho * v1 + h * (C * rho * v1 + P * F1)) / (base + h * P * (E + P1) / C);
+    u2 = (rho * v2 + h * (C * rho * v2 + P * F2)) / (base + h * P * (E + P2) / C);
+  }
+  const double uu = u0 * u0 + u1 * u1 + u2 * u2;
+  const bool to5 = ss > sa;  // Step 2 routing
+
+  // ------------------------------------------------ phase B: source sums
+  const A Au0 = A(u0), Au1 = A(u1), Au2 = A(u2), Auu = A(uu);
+  const A dsa = A(dt * sa), dss = A(dt * ss);
+  const A D0 = A(1.0 + dt * sa * C), E0 = A(dt * sa * C), AW0 = A(1.0 + dt * C * ss);
+  const A B0 = A(-dt * C * ss - dt * ss * uu / C), dssC = A(dt * ss / C);
+  A pk[KA];
+  A sm[kNsum];
+#pragma unroll
+  for (int r = 0; r < kNsum; ++r) sm[r] = A(0);
+#pragma unroll
+  for (int k = 0; k < KA; ++k) {
+    pk[k] = A(0);
+    if (k >= KG) continue;
+    const int m = m0 + k;
+    const A n0 = A(p.mu[m]), n1 = A(p.mu[NA + m]), n2 = A(p.mu[2 * NA + m]);
+    const A Wm = A(p.w[m]);
+    const A t = n0 * Au0 + n1 * Au1 + n2 * Au2;
+    const A D = D0 - dsa * t, aw = AW0 - dss * t;
+    const A rDa = fast_rcp(D * aw);
+    const A invD = aw * rDa, invaw = D * rDa;
+    const A e = E0 + A(3) * dsa * t;
+    const A gg = Auu + t * t;
+    const A b = B0 + A(2) * dss * t - dssC * t * t;
+    const A cm = A(-3) * dss * t;
+    const A r4 = to5 ? Ic[k] : Ic[k] + dF[k];
+    const A pm = r4 * invD + (to5 ? dF[k] : A(0));
+    pk[k] = pm;
+    const A WD = Wm * invD, Wa = Wm * invaw, Wad = Wa * invD;
+    sm[0] += WD * r4;
+    sm[1] += WD * e;
+    sm[2] += WD;
+    sm[3] += WD * t * r4;
+    sm[4] += WD * t * e;
+    sm[5] += WD * t;
+    sm[6] += WD * gg * r4;
+    sm[7] += WD * gg * e;
+    sm[8] += WD * gg;
+    sm[9] += Wa * b * pm;
+    sm[10] += Wa * pm;
+    sm[11] += Wa * b;
+    sm[12] += Wa * b * cm;
+    sm[13] += Wa;
+    sm[14] += Wa * cm;
+    sm[15] += Wad * b * e;
+    sm[16] += Wad * b;
+    sm[17] += Wad * e;
+    sm[18] += Wad;
+    const A WI = Wm * (Ic[k] + dF[k]);
+    sm[19] += n0 * WI;
+    sm[20] += n1 * WI;
+    sm[21] += n2 * WI;
+  }
+  double Sa[kChunk], Sb[kChunk];
+#pragma unroll
+  for (int r = 0; r < kChunk; ++r) {
+    Sa[r] = double(sm[r]);
+    Sb[r] = double(sm[kChunk + r]);
+  }
+  waves_reduce<kChunk, false>(Sa, sbuf, stot, g, G, lane);
+  waves_reduce<kChunk, false>(Sb, sbuf, stot, g, G, lane);
+  // Sa = sums 0..10, Sb = sums 11..21
+
+  // --------------------------------------------- solve (FP64, wave 0)
+  const double kap = dt * sa / C;
+  const double cv = rho * p.cvfac;
+  if (g == 0) {
+    const double qden = 1.0 + kap * Sa[8];
+    const double q0 = Sa[6] / qden, q1 = Sa[7] / qden;
+    const double j0 = Sa[0] - kap * Sa[2] * q0, j1 = Sa[1] - kap * Sa[2] * q1;
+    const double k0 = Sa[3] - kap * Sa[5] * q0, k1 = Sa[4] - kap * Sa[5] * q1;
+    const double beta = P * C * (1.0 - uu / (C * C)) * sa * dt;
+    const double g8 = 8.0 * kPi * P * sa * dt;
+    const double h0 = -g8 * (k0 - q0 / C) + kFourPi * beta * j0;
+    const double h1q = (-g8 * (k1 - q1 / C) - kFourPi * beta * (1.0 - j1)) * (1.0 / kFourPi);
+    double T = Tn;
+    int it;
+    bool conv = false;
+    for (it = 1; it <= p.maxit; ++it) {
+      const double T3 = T * T * T;
+      const double f = cv * (T - Tn) - h0 - h1q * T3 * T;
+      const double dT = f / (cv - 4.0 * h1q * T3);
+      T -= dT;
+      if (fabs(dT) <= p.rtol * fabs(T)) {
+        conv = true;
+        break;
+      }
+    }
+    if (act && (!conv || !(T > 0.0) || !isfinite(T))) atomicOr(p.status, 1);
+    const double X = T * T * T * T * (1.0 / kFourPi);
+    const double Q = q0 + q1 * X;
+    const double Sbr = Sa[9] + X * Sb[4] - kap * Q * Sb[5];
+    const double Sr5 = Sa[10] + X * Sb[6] - kap * Q * Sb[7];
+    const double a11 = 1.0 + Sb[0], a12 = Sb[1], a21 = Sb[2], a22 = 1.0 + Sb[3];
+    const double det = a11 * a22 - a12 * a21;
+    ssol[0 * 64 + lane] = X;
+    ssol[1 * 64 + lane] = kap * Q;
+    ssol[2 * 64 + lane] = (Sbr * a22 - a12 * Sr5) / det;
+    ssol[3 * 64 + lane] = (a11 * Sr5 - a21 * Sbr) / det;
+    ssol[4 * 64 + lane] = T;
+    ssol[5 * 64 + lane] = double(it);
+  }
+  __syncthreads();
+  const double X = ssol[lane], kQ = ssol[64 + lane], s1 = ssol[128 + lane],
+               s2 = ssol[192 + lane], T = ssol[256 + lane];
+  const double newton_it = ssol[320 + lane];
+
+  // --------------------------------------- phase C: new intensities
+  const A AX = A(X), AkQ = A(kQ), As1 = A(s1), As2 = A(s2);
+  double mo[kChunk];
+#pragma unroll
+  for (int r = 0; r < 10; ++r) mo[r] = 0.0;
+  mo[10] = 1.0e300;
+#pragma unroll
+  for (int k = 0; k < KA; ++k) {
+    if (k >= KG) continue;
+    const int m = m0 + k;
+    const double d0 = p.mu[m], d1 = p.mu[NA + m], d2 = p.mu[2 * NA + m];
+    const A t = A(d0) * Au0 + A(d1) * Au1 + A(d2) * Au2;
+    const A D = D0 - dsa * t, aw = AW0 - dss * t;
+    const A rDa = fast_rcp(D * aw);
+    const A e = E0 + A(3) * dsa * t;
+    const A cm = A(-3) * dss * t;
+    // I' = invaw (p - s1 - c s2) + invD invaw (e X - kappa Q)
+    const S Inew = S(D * rDa * (pk[k] - As1 - cm * As2) + rDa * (e * AX - AkQ));
+    if (act) Iout[(size_t)m * N + c] = Inew;
+    const double Iw = double(Inew) * p.w[m];
+    mo[0] += Iw;
+    mo[1] += d0 * Iw;
+    mo[2] += d1 * Iw;
+    mo[3] += d2 * Iw;
+    mo[4] += d0 * d0 * Iw;
+    mo[5] += d1 * d1 * Iw;
+    mo[6] += d2 * d2 * Iw;
+    mo[7] += d0 * d1 * Iw;
+    mo[8] += d0 * d2 * Iw;
+    mo[9] += d1 * d2 * Iw;
+    mo[10] = fmin(mo[10], double(Inew));
+  }
+  waves_reduce<kChunk, true>(mo, sbuf, stot, g, G, lane);
+#pragma unroll
+  for (int r = 0; r < 10; ++r) mo[r] *= kFourPi;
+
+  // ------------------------------------------------ Step 7 and outputs
+  const double f4 = kFourPi * P / C;
+  const double dm0 = -(P / C) * mo[1] + f4 * Sb[8];
+  const double dm1 = -(P / C) * mo[2] + f4 * Sb[9];
+  const double dm2 = -(P / C) * mo[3] + f4 * Sb[10];
+  const double mm0 = rho * v0, mm1 = rho * v1, mm2 = rho * v2;
+  const double ek =
+      (((mm0 + dm0) * (mm0 + dm0) + (mm1 + dm1) * (mm1 + dm1) + (mm2 + dm2) * (mm2 + dm2)) -
+       (mm0 * mm0 + mm1 * mm1 + mm2 * mm2)) /
+      (2.0 * rho);
+  const double deg = cv * (T - Tn) + ek;
+  if (act) {
+    // the per-cell stores are spread over the waves, 64 consecutive cells each
+    for (int f = g; f < 28; f += G) {
+      double val;
+      double *dst;
+      if (f < 10) {
+        val = mo[f];
+        dst = p.mom_out + (size_t)f * N;
+      } else if (f < 13) {
+        val = 3.0 * (f == 10 ? v0 : f == 11 ? v1 : v2) * mo[0] * (1.0 / kFourPi);
+        dst = p.mom_out + (size_t)f * N;
+      } else if (f == 13) {
+        val = T;
+        dst = p.T;
+      } else if (f == 14) {
+        if (!p.dEgas) continue;
+        val = (p.accumulate ? p.dEgas[c] : 0.0) + deg;
+        dst = p.dEgas;
+      } else if (f < 18) {
+        if (!p.dMom) continue;
+        const int k = f - 15;
+        val = (p.accumulate ? p.dMom[(size_t)k * N + c] : 0.0) + (k == 0 ? dm0 : k == 1 ? dm1 : dm2);
+        dst = p.dMom + (size_t)k * N;
+      } else if (f == 18) {
+        if (!p.oE) continue;
+        val = mo[0];
+        dst = p.oE;
+      } else if (f < 22) {
+        if (!p.oF) continue;
+        val = mo[f - 18];
+        dst = p.oF + (size_t)(f - 19) * N;
+      } else {
+        if (!p.oP) continue;
+        val = mo[f - 18];
+        dst = p.oP + (size_t)(f - 22) * N;
+      }
+      dst[c] = val;
+    }
+  }
+  if (g == 0) {
+    double tot[kNtot];
+    const double vol = p.vol;
+    const bool on = act;
+    tot[0] = on ? P * mo[0] * vol : 0.0;
+    tot[1] = on ? cv * T * vol : 0.0;
+    tot[2] = on ? deg * vol : 0.0;
+    tot[3] = on ? ek * vol : 0.0;
+    tot[4] = on ? dm0 * vol : 0.0;
+    tot[5] = on ? dm1 * vol : 0.0;
+    tot[6] = on ? dm2 * vol : 0.0;
+    tot[7] = on ? P / C * mo[1] * vol : 0.0;
+    tot[8] = on ? P / C * mo[2] * vol : 0.0;
+    tot[9] = on ? P / C * mo[3] * vol : 0.0;
+    tot[10] = on ? mo[10] : 1.0e300;
+    tot[11] = on ? newton_it : 0.0;
+#pragma unroll
+    for (int k = 0; k < kNtot; ++k) {
+      const double x = (k == 10) ? wave_min(tot[k]) : (k == 11) ? wave_max(tot[k]) : wave_sum(tot[k]);
+      if (lane == 0) p.partials[(size_t)blockIdx.x * kNtot + k] = x;
+    }
+  }
+}
+
+}  // namespace rtk

@@ -24,11 +24,9 @@ class Solver:
     """One radiative-transfer problem resident on the GPU.
 
     ``wl`` is a workload description (grid, parameters, fields, initial
-    intensity).  The library stores intensities cell-major, ``I[c][m]``;
-    ``I0`` (numpy array or device tensor) and ``state()["I"]`` use the
-    workload convention ``(nang, ncell)`` and are transposed on the way in and
-    out.  A device tensor ``I0`` avoids the host initialisation of large
-    problems."""
+    intensity).  Intensities are angle-major ``(nang, ncell)``, as in the
+    library; ``I0`` may be a numpy array or a device tensor (the latter
+    avoids the host initialisation of large problems)."""
 
     def __init__(self, wl, precision: str | None = None, mu=None, w=None,
                  estimate_v: bool = True, I0=None, T0=None, newton_rtol=1e-14,
@@ -61,12 +59,12 @@ class Solver:
         self.rho = put(wl.rho)
         self.T = put(wl.T if T0 is None else T0)
         self.v = put(wl.v).reshape(3, nc).contiguous()
-        self.I = [torch.empty((nc, self.nang), dtype=self.sdtype, device=dev) for _ in range(2)]
+        self.I = [torch.empty((self.nang, nc), dtype=self.sdtype, device=dev) for _ in range(2)]
         if I0 is None:
             I0 = wl.init(self.mu)
         if isinstance(I0, np.ndarray):
             I0 = torch.as_tensor(np.ascontiguousarray(I0, dtype=np.float64)).to(dev)
-        self.I[0].copy_(I0.T)
+        self.I[0].copy_(I0)
         self.E = torch.zeros(nc, **f64)
         self.F = torch.zeros((3, nc), **f64)
         self.P = torch.zeros((6, nc), **f64)
@@ -96,8 +94,7 @@ class Solver:
         return self
 
     def transport(self, dt: float | None = None):
-        """Transport increment as a device tensor in the library layout
-        (ncell, nang)."""
+        """Transport increment as a device tensor (nang, ncell)."""
         dF = self.torch.empty_like(self.I[0])
         rt.rt_transport(self.ctx, self.wl.dt if dt is None else dt, self.fields, dF,
                         self._stream())
@@ -118,7 +115,7 @@ class Solver:
     def state(self):
         """Host copies of the state and outputs (synchronises)."""
         self.torch.cuda.synchronize()
-        return dict(I=self.current().double().T.contiguous().cpu().numpy(), T=self.T.cpu().numpy(),
+        return dict(I=self.current().double().cpu().numpy(), T=self.T.cpu().numpy(),
                     E=self.E.cpu().numpy(), F=self.F.cpu().numpy(), P=self.P.cpu().numpy(),
                     dEgas=self.dEgas.cpu().numpy(), dMom=self.dMom.cpu().numpy(),
                     totals=self.totals.cpu().numpy())

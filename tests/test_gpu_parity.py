@@ -122,7 +122,7 @@ def test_transport_increment_matches_oracle():
                       bc=((W.BC_FIXED, W.BC_VACUUM), (0, 0), (W.BC_COPY, W.BC_FIXED)),
                       ghost_seed=8)
     s = _solver(wl)
-    dF = s.transport().double().T.contiguous().cpu().numpy()
+    dF = s.transport().double().cpu().numpy()
     s.close()
     prob = oracle.Problem(wl)
     I0 = wl.init(prob.mu)
