@@ -69,6 +69,16 @@ __device__ __forceinline__ double alpha_of(double sigma, double dl10) {
   return tau > 0.0 ? sqrt(-expm1(-tau) / tau) : 1.0;
 }
 
+// Blocks are dispatched round-robin over the eight XCDs (block b runs on XCD
+// b % 8, each with its own L2).  Renumbering them so that every XCD works
+// through one contiguous range of blocks keeps the stencil neighbours of a
+// block (the rows and planes next to it) in the same L2.
+__device__ __forceinline__ int xcd_block(int b, int nb) {
+  const int q = nb / 8;
+  if (b >= 8 * q) return b;
+  return (b % 8) * q + b / 8;
+}
+
 __device__ __forceinline__ double wave_sum(double x) {
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);

@@ -175,7 +175,10 @@ __global__ __launch_bounds__(64 * kMaxWaves) void k_step3(StepArgs p) {
   const int lane = threadIdx.x & 63;
   const int g = threadIdx.x >> 6;
   const int G = blockDim.x >> 6;
-  const int c0 = blockIdx.x * 64 + lane;
+  // FP32 storage runs two blocks per CU and gains from XCD-contiguous work;
+  // the FP64 kernel (one block per CU) measured faster in dispatch order.
+  const int blk = sizeof(S) == 4 ? xcd_block(blockIdx.x, gridDim.x) : (int)blockIdx.x;
+  const int c0 = blk * 64 + lane;
   const bool act = c0 < p.ncell;
   const int c = act ? c0 : p.ncell - 1;  // idle lanes shadow the last cell
   const int NA = p.nang;
@@ -490,7 +493,7 @@ __global__ __launch_bounds__(64 * kMaxWaves) void k_step3(StepArgs p) {
 #pragma unroll
     for (int k = 0; k < kNtot; ++k) {
       const double x = (k == 10) ? wave_min(tot[k]) : (k == 11) ? wave_max(tot[k]) : wave_sum(tot[k]);
-      if (lane == 0) p.partials[(size_t)blockIdx.x * kNtot + k] = x;
+      if (lane == 0) p.partials[(size_t)blk * kNtot + k] = x;
     }
   }
 }
