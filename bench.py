@@ -150,7 +150,7 @@ def main():
         print(json.dumps({"copy_probe_bytes_each_way": 8 * n, "launches": args.steps}))
         return
     wl = W.config2(nper=args.nper)
-    wname = f"box3d-{args.nper}^3-S8"
+    wname = f"box3d_{args.nper}cube_S8"
     print(f"bench: {wname} fp64 warmup={args.warmup} steps={args.steps}", file=sys.stderr,
           flush=True)
     if args.only:
@@ -170,7 +170,8 @@ def main():
         mixed = dict(value=rmx["value"], ms_per_step=rmx["ms_per_step"], dtype="f32 (I), f64 (T)",
                      roofline=dict(bound="hbm", achieved=rmx["achieved_gbs"], peak=HBM_PEAK_GBS,
                                    unit="GB/s", frac=rmx["achieved_gbs"] / HBM_PEAK_GBS,
-                                   traffic=load_traffic("k_step_fused_mixed", wname),
+                                   traffic=load_traffic("k_step3_mixed", wname),
+                                   kernel="rtk::k_step3<float, float, 10, true, true>",
                                    kernel_ms=rmx["kernel_ms"],
                                    bytes_per_launch=rmx["bytes_per_launch"]))
     cpu = None
@@ -197,8 +198,8 @@ def main():
                                                               "threads": r64["block_threads"]}},
         "roofline": {"bound": "hbm", "achieved": r64["achieved_gbs"], "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": r64["achieved_gbs"] / HBM_PEAK_GBS,
-                     "traffic": load_traffic("k_step_fused_fp64", wname),
-                     "kernel": "k_step<double,double,periodic,fused>",
+                     "traffic": load_traffic("k_step3_fp64", wname),
+                     "kernel": "rtk::k_step3<double, double, 10, true, true>",
                      "kernel_ms": r64["kernel_ms"], "bytes_per_launch": r64["bytes_per_launch"]},
         "fp32_mixed": mixed,
         "cpu_baseline": cpu,

@@ -45,6 +45,7 @@ extern "C" {
 #endif
 
 typedef enum rt_status {
+  RT_PENDING = 1,      /* (serving) the request has not completed yet        */
   RT_OK = 0,
   RT_EINVAL = -1,      /* invalid argument                                  */
   RT_ENOMEM = -2,      /* device or host allocation failed                  */
@@ -174,6 +175,11 @@ int rt_source_implicit(rt_ctx *ctx, double dt, const rt_fields *f, const void *d
  * are those after the last step. */
 int rt_step(rt_ctx *ctx, double dt, int nsteps, const rt_fields *f, rt_out *out,
             void *stream);
+
+/* Fills the intensity buffer I ([nang][ncell], storage type) with the
+ * equilibrium intensity T^4/(4 pi) of the device temperatures T ([ncell]
+ * doubles) in every direction (Section 2, code units), on the stream. */
+int rt_equilibrium_intensity(rt_ctx *ctx, const double *T, void *I, void *stream);
 
 /* Waits for the context's work and reports (then clears) the device status:
  * RT_OK or RT_ENOCONV. */

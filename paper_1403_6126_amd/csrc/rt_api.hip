@@ -1,5 +1,5 @@
-// Host side of the C ABI declared in include/rt.h: context management,
-// validation, and the launches of the step kernels.
+// Host side of the context API declared in include/rt.h: validation,
+// device-memory plan, and the launches of the per-call and per-step kernels.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -10,45 +10,193 @@
 
 #include "rt.h"
 #include "rt_fallback.hpp"
-#include "rt_step3.hpp"
+#include "rt_internal.hpp"
 
-using namespace rtk;
+namespace rtk {
 
-struct rt_ctx {
-  rt_grid g;
-  rt_params p;
-  int nang;
-  long long ncell;
-  int device;
-  bool all_periodic;
-  double cfl_sum;  // max over angles of sum_d |mu_d| / dx_d
-  std::vector<double> h_mu, h_w, h_ghost;
-  double *d_mu = nullptr, *d_w = nullptr, *d_ghost = nullptr;
-  void *I[2] = {nullptr, nullptr};
-  int cur = 0;
-  double *mom[2] = {nullptr, nullptr};  // [13][ncell]: E, F, P, 3vJ
-  int mom_cur = 0;
-  double *faces = nullptr;              // [3][3][ncell] interface table of the call
-  int waves = 0;                        // waves per block of k_step3 (0: thread-per-cell kernel)
-  bool mom_valid = false;
-  double *partials = nullptr;
-  double *acc = nullptr;
-  int *status = nullptr;
-  long long nblocks = 0;
-  bool profile = false;
-  std::vector<hipEvent_t> ev_pool;
-  std::vector<std::pair<hipEvent_t, hipEvent_t>> pending;
-  double prof_ms = 0.0;
-  int prof_n = 0;
-};
+// Interface table and IV basis (once per call).  faces[(d*3 + j)*ncell + c]
+// for the face between the cell below c along axis d (wrapped; the edge cell
+// itself at a non-periodic low boundary, whose ghost copies it) and c:
+// j = 0 alpha, 1 hv = (1 - |u| dt/dx)/2, 2 u.  wv = 3 v E/(4pi) of the
+// current moments into mom[10..12].
+__global__ __launch_bounds__(kBlock) void k_faces(StepArgs p, double *faces, double *mom) {
+  const int c = blockIdx.x * kBlock + threadIdx.x;
+  if (c >= p.ncell) return;
+  const size_t N = (size_t)p.ncell;
+  const double sig_c = p.sa[c] + p.ss[c];
+  const int q[3] = {c % p.n[0], (c / p.n[0]) % p.n[1], c / (p.n[0] * p.n[1])};
+  for (int d = 0; d < p.ndim; ++d) {
+    int cl;
+    if (q[d] > 0)
+      cl = c - p.stride[d];
+    else if (p.bc[d][0] == kPeriodic)
+      cl = c + (p.n[d] - 1) * p.stride[d];
+    else
+      cl = c;
+    const double sig = 0.5 * ((p.sa[cl] + p.ss[cl]) + sig_c);
+    const double u = 0.5 * (p.v[(size_t)d * N + cl] + p.v[(size_t)d * N + c]);
+    faces[(size_t)(d * 3 + 0) * N + c] = alpha_of(sig, p.dl10[d]);
+    faces[(size_t)(d * 3 + 1) * N + c] = 0.5 * (1.0 - fabs(u) * p.dt_dx[d]);
+    faces[(size_t)(d * 3 + 2) * N + c] = u;
+  }
+  const double J = mom[c] * (1.0 / kFourPi);
+  for (int k = 0; k < 3; ++k) mom[(size_t)(10 + k) * N + c] = 3.0 * p.v[(size_t)k * N + c] * J;
+}
+
+__global__ __launch_bounds__(kVLanes) void k_totals(const double *partials, int nblocks,
+                                                    double *acc, int reset, double *out) {
+  __shared__ double red[kNtot * kVWaves];
+  totals_reduce(partials, nblocks, acc, reset, out, red);
+}
+
+
+// I[m][c] = T[c]^4 / (4 pi), the equilibrium intensity in every direction.
+template <typename S>
+__global__ __launch_bounds__(kBlock) void k_equilibrium(const double *T, S *I, int ncell,
+                                                        int nang) {
+  const int c = blockIdx.x * kBlock + threadIdx.x;
+  if (c >= ncell) return;
+  const double t = T[c];
+  const S b = S((t * t) * (t * t) / kFourPi);
+  for (int m = 0; m < nang; ++m) I[(size_t)m * ncell + c] = b;
+}
 
 namespace {
 
 bool hip_ok(hipError_t e) { return e == hipSuccess; }
 
-int storage_bytes(const rt_ctx *c) { return c->p.precision == RT_FP32_MIXED ? 4 : 8; }
+// Kernel launches report failure through hipGetLastError only; an error left
+// by an earlier call of this thread (already returned by that call) is
+// cleared first so that the check after a launch sees only the launch.
+void clear_stale_error() { (void)hipGetLastError(); }
 
-void fill_args(const rt_ctx *c, double dt, const rt_fields *f, StepArgs &a) {
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+KShape pick_shape(int nang, bool periodic) {
+  KShape k;
+  k.periodic = periodic;
+  const int ng = (nang + kAnglesPerWave - 1) / kAnglesPerWave;
+  const int G = ng < kMaxWaves ? ng : kMaxWaves;
+  const int NG = (ng + G - 1) / G;
+  if (NG <= kMaxGroupsPerWave) {
+    k.waves = G;
+    k.groups = NG;
+  }
+  return k;
+}
+
+long long cell_blocks(const rt_ctx *c) { return (c->ncell + kBlock - 1) / kBlock; }
+
+bool fields_ok(const rt_fields *f) {
+  return f && f->sigma_a && f->sigma_s && f->rho && f->T && f->v;
+}
+
+void launch_step(const rt_ctx *c, const StepArgs &a, bool fused, hipStream_t s) {
+  clear_stale_error();
+  if (c->p.precision == RT_FP32_MIXED)
+    launch_step_f32(a, c->shape, fused, ctx_step_blocks(c), s);
+  else
+    launch_step_f64(a, c->shape, fused, ctx_step_blocks(c), s);
+}
+
+void launch_transport(const rt_ctx *c, const StepArgs &a, hipStream_t s) {
+  clear_stale_error();
+  dim3 g((unsigned)cell_blocks(c)), b(kBlock);
+  if (c->p.precision == RT_FP32_MIXED) {
+    if (c->all_periodic)
+      hipLaunchKernelGGL((k_transport<float, float, true>), g, b, 0, s, a);
+    else
+      hipLaunchKernelGGL((k_transport<float, float, false>), g, b, 0, s, a);
+  } else {
+    if (c->all_periodic)
+      hipLaunchKernelGGL((k_transport<double, double, true>), g, b, 0, s, a);
+    else
+      hipLaunchKernelGGL((k_transport<double, double, false>), g, b, 0, s, a);
+  }
+}
+
+void launch_moments(const rt_ctx *c, const StepArgs &a, hipStream_t s) {
+  clear_stale_error();
+  dim3 g((unsigned)cell_blocks(c)), b(kBlock);
+  if (c->p.precision == RT_FP32_MIXED)
+    hipLaunchKernelGGL(k_moments<float>, g, b, 0, s, a);
+  else
+    hipLaunchKernelGGL(k_moments<double>, g, b, 0, s, a);
+}
+
+int ensure_moments(rt_ctx *c, hipStream_t s) {
+  if (c->mom_valid) return RT_OK;
+  return ctx_moments(c, s);
+}
+
+hipEvent_t take_event(rt_ctx *c) {
+  if (!c->ev_pool.empty()) {
+    hipEvent_t e = c->ev_pool.back();
+    c->ev_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+// One step (fused or from a given dF); swaps the current buffers.
+int one_step(rt_ctx *c, double dt, const rt_fields *f, const void *dF, bool fused, rt_out *o,
+             bool first, bool last, hipStream_t s) {
+  StepArgs a;
+  ctx_fill_args(c, dt, f, a);
+  a.I_in = c->I[c->cur];
+  a.I_out = c->I[1 - c->cur];
+  a.mom_in = c->mom[c->mom_cur];
+  a.mom_out = c->mom[1 - c->mom_cur];
+  a.dF_in = dF;
+  a.accumulate = first ? 0 : 1;
+  if (o) {
+    a.dEgas = o->dEgas;
+    a.dMom = o->dMom;
+    if (last) {
+      a.oE = o->Er;
+      a.oF = o->Fr;
+      a.oP = o->Pr;
+    }
+  }
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (c->profile && fused) {
+    e0 = take_event(c);
+    e1 = take_event(c);
+    if (e0 && e1) hipEventRecord(e0, s);
+  }
+  launch_step(c, a, fused, s);
+  if (!hip_ok(hipGetLastError())) return RT_EDEVICE;
+  if (e0 && e1) {
+    hipEventRecord(e1, s);
+    c->pending.emplace_back(e0, e1);
+  }
+  hipLaunchKernelGGL(k_totals, dim3(1), dim3(kVLanes), 0, s, c->partials,
+                     (int)ctx_step_blocks(c), c->acc, first ? 1 : 0,
+                     (last && o) ? o->totals : nullptr);
+  if (!hip_ok(hipGetLastError())) return RT_EDEVICE;
+  c->cur = 1 - c->cur;
+  c->mom_cur = 1 - c->mom_cur;
+  c->mom_valid = true;
+  return RT_OK;
+}
+
+}  // namespace
+
+long long ctx_step_blocks(const rt_ctx *c) {
+  return c->shape.waves ? (c->ncell + 63) / 64 : (c->ncell + kBlock - 1) / kBlock;
+}
+
+int ctx_storage_bytes(const rt_ctx *c) { return c->p.precision == RT_FP32_MIXED ? 4 : 8; }
+
+int ctx_check_dt(const rt_ctx *c, double dt) {
+  if (!(dt > 0.0) || !std::isfinite(dt)) return RT_EINVAL;
+  if (c->p.c * dt * c->cfl_sum > 1.0 + 1e-12) return RT_ECFL;
+  return RT_OK;
+}
+
+void ctx_fill_args(const rt_ctx *c, double dt, const rt_fields *f, StepArgs &a) {
   std::memset(&a, 0, sizeof(a));
   a.ndim = c->g.ndim;
   for (int d = 0; d < 3; ++d) {
@@ -86,183 +234,10 @@ void fill_args(const rt_ctx *c, double dt, const rt_fields *f, StepArgs &a) {
   }
   a.status = c->status;
   a.partials = c->partials;
+  a.nparts = (int)ctx_step_blocks(c);
 }
 
-bool fields_ok(const rt_fields *f) {
-  return f && f->sigma_a && f->sigma_s && f->rho && f->T && f->v;
-}
-
-int check_dt(const rt_ctx *c, double dt) {
-  if (!(dt > 0.0) || !std::isfinite(dt)) return RT_EINVAL;
-  if (c->p.c * dt * c->cfl_sum > 1.0 + 1e-12) return RT_ECFL;
-  return RT_OK;
-}
-
-// Waves per block of the wave-group kernel (10 angles per wave), or 0 when
-// the angle set is larger than it handles and the thread-per-cell kernel
-// runs instead.
-constexpr int kAnglesPerWave = 10;
-int pick_waves(int nang) {
-  const int G = (nang + kAnglesPerWave - 1) / kAnglesPerWave;
-  return G <= kMaxWaves ? G : 0;
-}
-
-long long step_blocks(const rt_ctx *c) {
-  return c->waves ? (c->ncell + 63) / 64 : (c->ncell + kBlock - 1) / kBlock;
-}
-long long cell_blocks(const rt_ctx *c) { return (c->ncell + kBlock - 1) / kBlock; }
-
-template <typename S, typename A, bool FUSED>
-void launch_step_t(const rt_ctx *c, const StepArgs &a, hipStream_t s) {
-  if (c->waves) {
-    dim3 g((unsigned)step_blocks(c)), b(64 * c->waves);
-    if (c->all_periodic)
-      hipLaunchKernelGGL((k_step3<S, A, kAnglesPerWave, true, FUSED>), g, b, 0, s, a);
-    else
-      hipLaunchKernelGGL((k_step3<S, A, kAnglesPerWave, false, FUSED>), g, b, 0, s, a);
-  } else {
-    dim3 g((unsigned)step_blocks(c)), b(kBlock);
-    if (c->all_periodic)
-      hipLaunchKernelGGL((k_step<S, A, true, FUSED>), g, b, 0, s, a);
-    else
-      hipLaunchKernelGGL((k_step<S, A, false, FUSED>), g, b, 0, s, a);
-  }
-}
-
-void launch_step(const rt_ctx *c, const StepArgs &a, bool fused, hipStream_t s) {
-  if (c->p.precision == RT_FP32_MIXED) {
-    if (fused)
-      launch_step_t<float, float, true>(c, a, s);
-    else
-      launch_step_t<float, float, false>(c, a, s);
-  } else {
-    if (fused)
-      launch_step_t<double, double, true>(c, a, s);
-    else
-      launch_step_t<double, double, false>(c, a, s);
-  }
-}
-
-void launch_transport(const rt_ctx *c, const StepArgs &a, hipStream_t s) {
-  dim3 g((unsigned)cell_blocks(c)), b(kBlock);
-  if (c->p.precision == RT_FP32_MIXED) {
-    if (c->all_periodic)
-      hipLaunchKernelGGL((k_transport<float, float, true>), g, b, 0, s, a);
-    else
-      hipLaunchKernelGGL((k_transport<float, float, false>), g, b, 0, s, a);
-  } else {
-    if (c->all_periodic)
-      hipLaunchKernelGGL((k_transport<double, double, true>), g, b, 0, s, a);
-    else
-      hipLaunchKernelGGL((k_transport<double, double, false>), g, b, 0, s, a);
-  }
-}
-
-void launch_moments(const rt_ctx *c, const StepArgs &a, hipStream_t s) {
-  dim3 g((unsigned)cell_blocks(c)), b(kBlock);
-  if (c->p.precision == RT_FP32_MIXED)
-    hipLaunchKernelGGL(k_moments<float>, g, b, 0, s, a);
-  else
-    hipLaunchKernelGGL(k_moments<double>, g, b, 0, s, a);
-}
-
-int ensure_moments(rt_ctx *c, hipStream_t s) {
-  if (c->mom_valid) return RT_OK;
-  StepArgs a;
-  fill_args(c, 1.0, nullptr, a);
-  a.I_in = c->I[c->cur];
-  a.mom_out = c->mom[c->mom_cur];
-  launch_moments(c, a, s);
-  if (!hip_ok(hipGetLastError())) return RT_EDEVICE;
-  c->mom_valid = true;
-  return RT_OK;
-}
-
-// Per-call tables: interface alpha / flow speed / IV Courant factor for this
-// dt and fields, and 3 v J of the current moments.
-int prepare_call(rt_ctx *c, double dt, const rt_fields *f, hipStream_t s) {
-  StepArgs a;
-  fill_args(c, dt, f, a);
-  const long long nb = (c->ncell + kBlock - 1) / kBlock;
-  hipLaunchKernelGGL(k_faces, dim3((unsigned)nb), dim3(kBlock), 0, s, a, c->faces,
-                     c->mom[c->mom_cur]);
-  return hip_ok(hipGetLastError()) ? RT_OK : RT_EDEVICE;
-}
-
-hipEvent_t take_event(rt_ctx *c) {
-  if (!c->ev_pool.empty()) {
-    hipEvent_t e = c->ev_pool.back();
-    c->ev_pool.pop_back();
-    return e;
-  }
-  hipEvent_t e = nullptr;
-  if (hipEventCreate(&e) != hipSuccess) return nullptr;
-  return e;
-}
-
-// One step (fused or from a given dF); swaps the current buffers.
-int one_step(rt_ctx *c, double dt, const rt_fields *f, const void *dF, bool fused, rt_out *o,
-             bool first, bool last, hipStream_t s) {
-  StepArgs a;
-  fill_args(c, dt, f, a);
-  a.I_in = c->I[c->cur];
-  a.I_out = c->I[1 - c->cur];
-  a.mom_in = c->mom[c->mom_cur];
-  a.mom_out = c->mom[1 - c->mom_cur];
-  a.dF_in = dF;
-  a.accumulate = first ? 0 : 1;
-  if (o) {
-    a.dEgas = o->dEgas;
-    a.dMom = o->dMom;
-    if (last) {
-      a.oE = o->Er;
-      a.oF = o->Fr;
-      a.oP = o->Pr;
-    }
-  }
-  hipEvent_t e0 = nullptr, e1 = nullptr;
-  if (c->profile && fused) {
-    e0 = take_event(c);
-    e1 = take_event(c);
-    if (e0 && e1) hipEventRecord(e0, s);
-  }
-  launch_step(c, a, fused, s);
-  if (!hip_ok(hipGetLastError())) return RT_EDEVICE;
-  if (e0 && e1) {
-    hipEventRecord(e1, s);
-    c->pending.emplace_back(e0, e1);
-  }
-  hipLaunchKernelGGL(k_totals, dim3(1), dim3(kBlock), 0, s, c->partials, (int)step_blocks(c),
-                     c->acc, first ? 1 : 0, (last && o) ? o->totals : nullptr);
-  if (!hip_ok(hipGetLastError())) return RT_EDEVICE;
-  c->cur = 1 - c->cur;
-  c->mom_cur = 1 - c->mom_cur;
-  c->mom_valid = true;
-  return RT_OK;
-}
-
-}  // namespace
-
-extern "C" {
-
-const char *rt_strerror(int st) {
-  switch (st) {
-    case RT_OK: return "ok";
-    case RT_EINVAL: return "invalid argument";
-    case RT_ENOMEM: return "out of memory";
-    case RT_EDEVICE: return "HIP runtime error";
-    case RT_ECFL: return "time step violates the transport CFL limit";
-    case RT_ENOCONV: return "temperature Newton iteration failed";
-    case RT_EBADQUAD: return "invalid angle set (weights or direction norms)";
-    case RT_ESTATE: return "call order violated (no intensity bound?)";
-    case RT_EUNSUPPORTED: return "unsupported request";
-    default: return "unknown status";
-  }
-}
-
-int rt_create(const rt_grid *g, const rt_angles *an, const rt_params *p, rt_ctx **out) {
-  if (!out) return RT_EINVAL;
-  *out = nullptr;
+int ctx_init_host(const rt_grid *g, const rt_angles *an, const rt_params *p, rt_ctx *c) {
   if (!g || !an || !p) return RT_EINVAL;
   if (g->ndim < 1 || g->ndim > 3) return RT_EINVAL;
   long long nc = 1;
@@ -293,20 +268,17 @@ int rt_create(const rt_grid *g, const rt_angles *an, const rt_params *p, rt_ctx 
     return RT_EINVAL;
   if (p->precision != RT_FP64 && p->precision != RT_FP32_MIXED) return RT_EINVAL;
 
-  rt_ctx *c = new (std::nothrow) rt_ctx();
-  if (!c) return RT_ENOMEM;
   c->g = *g;
   c->p = *p;
   if (!(c->p.newton_rtol > 0.0)) c->p.newton_rtol = 1e-14;
   if (c->p.newton_maxit <= 0) c->p.newton_maxit = 64;
   c->nang = an->n;
   c->ncell = nc;
-  hipGetDevice(&c->device);
   c->all_periodic = true;
   for (int d = 0; d < g->ndim; ++d)
     if (g->bc[d][0] != RT_BC_PERIODIC) c->all_periodic = false;
   const int N = an->n;
-  c->h_mu.assign(3 * N, 0.0);
+  c->h_mu.assign(3 * (size_t)N, 0.0);
   c->h_w.assign(an->w, an->w + N);
   c->h_ghost.assign(6 * (size_t)N, 0.0);
   c->cfl_sum = 0.0;
@@ -318,28 +290,160 @@ int rt_create(const rt_grid *g, const rt_angles *an, const rt_params *p, rt_ctx 
     }
     if (s > c->cfl_sum) c->cfl_sum = s;
   }
-  c->waves = pick_waves(N);
+  c->shape = pick_shape(N, c->all_periodic);
   c->nblocks = (nc + 63) / 64;  // enough partial-total rows for either kernel
-  bool ok = hip_ok(hipMalloc(&c->d_mu, sizeof(double) * 3 * N)) &&
-            hip_ok(hipMalloc(&c->d_w, sizeof(double) * N)) &&
-            hip_ok(hipMalloc(&c->d_ghost, sizeof(double) * 6 * N)) &&
-            hip_ok(hipMalloc(&c->mom[0], sizeof(double) * kNmomX * nc)) &&
-            hip_ok(hipMalloc(&c->mom[1], sizeof(double) * kNmomX * nc)) &&
-            hip_ok(hipMalloc(&c->faces, sizeof(double) * 9 * nc)) &&
-            hip_ok(hipMalloc(&c->partials, sizeof(double) * kNtot * c->nblocks)) &&
-            hip_ok(hipMalloc(&c->acc, sizeof(double) * kNtot)) &&
-            hip_ok(hipMalloc(&c->status, sizeof(int)));
-  if (ok)
-    ok = hip_ok(hipMemcpy(c->d_mu, c->h_mu.data(), sizeof(double) * 3 * N,
-                          hipMemcpyHostToDevice)) &&
-         hip_ok(hipMemcpy(c->d_w, c->h_w.data(), sizeof(double) * N, hipMemcpyHostToDevice)) &&
-         hip_ok(hipMemcpy(c->d_ghost, c->h_ghost.data(), sizeof(double) * 6 * N,
-                          hipMemcpyHostToDevice)) &&
-         hip_ok(hipMemset(c->status, 0, sizeof(int))) &&
-         hip_ok(hipMemset(c->acc, 0, sizeof(double) * kNtot));
-  if (!ok) {
-    rt_destroy(c);
+  return RT_OK;
+}
+
+namespace {
+// Scratch layout: offsets of the pieces in one block.
+struct Plan {
+  size_t mu, w, ghost, mom0, mom1, faces, partials, acc, status, total;
+};
+Plan plan_of(const rt_ctx *c) {
+  Plan q;
+  const size_t N = c->nang, nc = c->ncell;
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    const size_t at = o;
+    o += align256(bytes);
+    return at;
+  };
+  q.mu = take(sizeof(double) * 3 * N);
+  q.w = take(sizeof(double) * N);
+  q.ghost = take(sizeof(double) * 6 * N);
+  q.mom0 = take(sizeof(double) * kNmomX * nc);
+  q.mom1 = take(sizeof(double) * kNmomX * nc);
+  q.faces = take(sizeof(double) * 9 * nc);
+  q.partials = take(sizeof(double) * kNtot * c->nblocks);
+  q.acc = take(sizeof(double) * kNtot);
+  q.status = take(sizeof(int));
+  q.total = o;
+  return q;
+}
+}  // namespace
+
+size_t ctx_scratch_bytes(const rt_ctx *c) { return plan_of(c).total; }
+
+int ctx_attach_scratch(rt_ctx *c, char *base, hipStream_t s) {
+  const Plan q = plan_of(c);
+  const size_t N = c->nang;
+  c->d_mu = reinterpret_cast<double *>(base + q.mu);
+  c->d_w = reinterpret_cast<double *>(base + q.w);
+  c->d_ghost = reinterpret_cast<double *>(base + q.ghost);
+  c->mom[0] = reinterpret_cast<double *>(base + q.mom0);
+  c->mom[1] = reinterpret_cast<double *>(base + q.mom1);
+  c->faces = reinterpret_cast<double *>(base + q.faces);
+  c->partials = reinterpret_cast<double *>(base + q.partials);
+  c->acc = reinterpret_cast<double *>(base + q.acc);
+  c->status = reinterpret_cast<int *>(base + q.status);
+  const bool ok =
+      hip_ok(hipMemcpyAsync(c->d_mu, c->h_mu.data(), sizeof(double) * 3 * N,
+                            hipMemcpyHostToDevice, s)) &&
+      hip_ok(hipMemcpyAsync(c->d_w, c->h_w.data(), sizeof(double) * N, hipMemcpyHostToDevice,
+                            s)) &&
+      hip_ok(hipMemcpyAsync(c->d_ghost, c->h_ghost.data(), sizeof(double) * 6 * N,
+                            hipMemcpyHostToDevice, s)) &&
+      hip_ok(hipMemsetAsync(c->status, 0, sizeof(int), s)) &&
+      hip_ok(hipMemsetAsync(c->acc, 0, sizeof(double) * kNtot, s));
+  return ok ? RT_OK : RT_EDEVICE;
+}
+
+int ctx_moments(rt_ctx *c, hipStream_t s) {
+  StepArgs a;
+  ctx_fill_args(c, 1.0, nullptr, a);
+  a.I_in = c->I[c->cur];
+  a.mom_out = c->mom[c->mom_cur];
+  launch_moments(c, a, s);
+  if (!hip_ok(hipGetLastError())) return RT_EDEVICE;
+  c->mom_valid = true;
+  return RT_OK;
+}
+
+// Per-call tables: interface alpha / flow speed / IV Courant factor for this
+// dt and fields, and 3 v J of the current moments.
+int ctx_prepare_call(rt_ctx *c, double dt, const rt_fields *f, hipStream_t s) {
+  StepArgs a;
+  ctx_fill_args(c, dt, f, a);
+  clear_stale_error();
+  hipLaunchKernelGGL(k_faces, dim3((unsigned)cell_blocks(c)), dim3(kBlock), 0, s, a, c->faces,
+                     c->mom[c->mom_cur]);
+  return hip_ok(hipGetLastError()) ? RT_OK : RT_EDEVICE;
+}
+
+int ctx_step(rt_ctx *c, double dt, int nsteps, const rt_fields *f, rt_out *o, hipStream_t s) {
+  int st = ensure_moments(c, s);
+  if (st != RT_OK) return st;
+  st = ctx_prepare_call(c, dt, f, s);
+  if (st != RT_OK) return st;
+  return ctx_step_range(c, dt, f, o, 0, nsteps, nsteps, s);
+}
+
+int ctx_step_range(rt_ctx *c, double dt, const rt_fields *f, rt_out *o, int k0, int k1,
+                   int ntotal, hipStream_t s) {
+  for (int k = k0; k < k1; ++k) {
+    const int st = one_step(c, dt, f, nullptr, true, o, k == 0, k == ntotal - 1, s);
+    if (st != RT_OK) return st;
+  }
+  return RT_OK;
+}
+
+int ctx_init_equilibrium(rt_ctx *c, const double *T, void *I, hipStream_t s) {
+  dim3 g((unsigned)cell_blocks(c)), b(kBlock);
+  clear_stale_error();
+  if (c->p.precision == RT_FP32_MIXED)
+    hipLaunchKernelGGL(k_equilibrium<float>, g, b, 0, s, T, static_cast<float *>(I),
+                       (int)c->ncell, c->nang);
+  else
+    hipLaunchKernelGGL(k_equilibrium<double>, g, b, 0, s, T, static_cast<double *>(I),
+                       (int)c->ncell, c->nang);
+  return hip_ok(hipGetLastError()) ? RT_OK : RT_EDEVICE;
+}
+
+}  // namespace rtk
+
+using namespace rtk;
+
+extern "C" {
+
+const char *rt_strerror(int st) {
+  switch (st) {
+    case RT_OK: return "ok";
+    case RT_PENDING: return "request still in flight";
+    case RT_EINVAL: return "invalid argument";
+    case RT_ENOMEM: return "out of memory";
+    case RT_EDEVICE: return "HIP runtime error";
+    case RT_ECFL: return "time step violates the transport CFL limit";
+    case RT_ENOCONV: return "temperature Newton iteration failed";
+    case RT_EBADQUAD: return "invalid angle set (weights or direction norms)";
+    case RT_ESTATE: return "call order violated (no intensity bound?)";
+    case RT_EUNSUPPORTED: return "unsupported request";
+    default: return "unknown status";
+  }
+}
+
+int rt_create(const rt_grid *g, const rt_angles *an, const rt_params *p, rt_ctx **out) {
+  if (!out) return RT_EINVAL;
+  *out = nullptr;
+  rt_ctx *c = new (std::nothrow) rt_ctx();
+  if (!c) return RT_ENOMEM;
+  int st = ctx_init_host(g, an, p, c);
+  if (st != RT_OK) {
+    delete c;
+    return st;
+  }
+  hipGetDevice(&c->device);
+  char *base = nullptr;
+  if (!hip_ok(hipMalloc(&base, ctx_scratch_bytes(c)))) {
+    delete c;
     return RT_ENOMEM;
+  }
+  c->owns_device = true;
+  st = ctx_attach_scratch(c, base, nullptr);
+  if (st == RT_OK && !hip_ok(hipStreamSynchronize(nullptr))) st = RT_EDEVICE;
+  if (st != RT_OK) {
+    rt_destroy(c);
+    return st;
   }
   *out = c;
   return RT_OK;
@@ -348,15 +452,8 @@ int rt_create(const rt_grid *g, const rt_angles *an, const rt_params *p, rt_ctx 
 int rt_destroy(rt_ctx *c) {
   if (!c) return RT_EINVAL;
   hipDeviceSynchronize();
-  hipFree(c->d_mu);
-  hipFree(c->d_w);
-  hipFree(c->d_ghost);
-  hipFree(c->mom[0]);
-  hipFree(c->mom[1]);
-  hipFree(c->faces);
-  hipFree(c->partials);
-  hipFree(c->acc);
-  hipFree(c->status);
+  // the scratch block starts at the angle table
+  if (c->owns_device && c->d_mu) hipFree(c->d_mu);
   for (auto &pr : c->pending) {
     hipEventDestroy(pr.first);
     hipEventDestroy(pr.second);
@@ -397,7 +494,7 @@ int rt_moments(rt_ctx *c, rt_out *o, void *stream) {
   if (!c->I[0]) return RT_ESTATE;
   hipStream_t s = (hipStream_t)stream;
   StepArgs a;
-  fill_args(c, 1.0, nullptr, a);
+  ctx_fill_args(c, 1.0, nullptr, a);
   a.I_in = c->I[c->cur];
   a.mom_out = c->mom[c->mom_cur];
   if (o) {
@@ -414,15 +511,15 @@ int rt_moments(rt_ctx *c, rt_out *o, void *stream) {
 int rt_transport(rt_ctx *c, double dt, const rt_fields *f, void *dF, void *stream) {
   if (!c || !dF || !fields_ok(f)) return RT_EINVAL;
   if (!c->I[0]) return RT_ESTATE;
-  int st = check_dt(c, dt);
+  int st = ctx_check_dt(c, dt);
   if (st != RT_OK) return st;
   hipStream_t s = (hipStream_t)stream;
   st = ensure_moments(c, s);
   if (st != RT_OK) return st;
-  st = prepare_call(c, dt, f, s);
+  st = ctx_prepare_call(c, dt, f, s);
   if (st != RT_OK) return st;
   StepArgs a;
-  fill_args(c, dt, f, a);
+  ctx_fill_args(c, dt, f, a);
   a.I_in = c->I[c->cur];
   a.mom_in = c->mom[c->mom_cur];
   a.dF_out = dF;
@@ -438,7 +535,7 @@ int rt_source_implicit(rt_ctx *c, double dt, const rt_fields *f, const void *dF,
   hipStream_t s = (hipStream_t)stream;
   int st = ensure_moments(c, s);
   if (st != RT_OK) return st;
-  st = prepare_call(c, dt, f, s);
+  st = ctx_prepare_call(c, dt, f, s);
   if (st != RT_OK) return st;
   return one_step(c, dt, f, dF, false, o, true, true, s);
 }
@@ -446,18 +543,15 @@ int rt_source_implicit(rt_ctx *c, double dt, const rt_fields *f, const void *dF,
 int rt_step(rt_ctx *c, double dt, int nsteps, const rt_fields *f, rt_out *o, void *stream) {
   if (!c || !fields_ok(f) || nsteps < 0) return RT_EINVAL;
   if (!c->I[0]) return RT_ESTATE;
-  int st = check_dt(c, dt);
+  int st = ctx_check_dt(c, dt);
   if (st != RT_OK) return st;
-  hipStream_t s = (hipStream_t)stream;
-  st = ensure_moments(c, s);
-  if (st != RT_OK) return st;
-  st = prepare_call(c, dt, f, s);
-  if (st != RT_OK) return st;
-  for (int k = 0; k < nsteps; ++k) {
-    st = one_step(c, dt, f, nullptr, true, o, k == 0, k == nsteps - 1, s);
-    if (st != RT_OK) return st;
-  }
-  return RT_OK;
+  return ctx_step(c, dt, nsteps, f, o, (hipStream_t)stream);
+}
+
+int rt_equilibrium_intensity(rt_ctx *c, const double *T, void *I, void *stream) {
+  if (!c || !T || !I) return RT_EINVAL;
+  if (I == c->I[c->cur]) c->mom_valid = false;
+  return ctx_init_equilibrium(c, T, I, (hipStream_t)stream);
 }
 
 int rt_sync_status(rt_ctx *c) {
@@ -501,9 +595,9 @@ int rt_get_info(rt_ctx *c, rt_info *info) {
   if (!c || !info) return RT_EINVAL;
   info->nang = c->nang;
   info->ncell = c->ncell;
-  info->storage_bytes = storage_bytes(c);
-  info->block_threads = c->waves ? 64 * c->waves : kBlock;
-  info->grid_blocks = step_blocks(c);
+  info->storage_bytes = ctx_storage_bytes(c);
+  info->block_threads = c->shape.waves ? 64 * c->shape.waves : kBlock;
+  info->grid_blocks = ctx_step_blocks(c);
   return RT_OK;
 }
 

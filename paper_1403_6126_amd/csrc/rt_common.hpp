@@ -15,6 +15,7 @@ constexpr double kPi = 3.1415926535897932384626433832795;
 
 enum BcKind : int { kPeriodic = 0, kFixed = 1, kCopy = 2, kVacuum = 3 };
 constexpr int kNmomX = 13;  // moments (10) + 3 v J (3)
+constexpr int kMaxWaves = 8;  // waves per block of the wave-group kernel
 
 // Arguments of every step kernel (passed by value).
 struct StepArgs {
@@ -37,16 +38,14 @@ struct StepArgs {
   double *oE, *oF, *oP;  // optional copies of the new moments
   double *dEgas, *dMom;  // optional per-cell sums over the call
   int accumulate;
-  double *partials;      // [grid][kNtot]
+  double *partials;      // [kNtot][nparts] per-block partial totals
+  int nparts;            // rows of partials: blocks (tiles of cells) of the launch
   int *status;
   const void *I_in;
   void *I_out;
   const void *dF_in;     // unfused source step: transport increment (nullable)
   void *dF_out;          // transport-only output
 };
-
-
-
 
 // ----------------------------------------------------------------- helpers
 // van Leer harmonic-mean slope of the one-sided differences (zero at
@@ -96,7 +95,7 @@ __device__ __forceinline__ double wave_max(double x) {
 }
 
 // Deterministic per-block reduction of the totals vector into partials.
-__device__ __forceinline__ void block_totals(double (&t)[kNtot], double *partials) {
+__device__ __forceinline__ void block_totals(double (&t)[kNtot], double *partials, int nparts) {
   __shared__ double red[kBlock / 64][kNtot];
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
 #pragma unroll
@@ -111,47 +110,60 @@ __device__ __forceinline__ void block_totals(double (&t)[kNtot], double *partial
     double x = red[0][k];
     for (int q = 1; q < kBlock / 64; ++q)
       x = (k == 10) ? fmin(x, red[q][k]) : (k == 11) ? fmax(x, red[q][k]) : x + red[q][k];
-    partials[(size_t)blockIdx.x * kNtot + k] = x;
+    partials[(size_t)k * nparts + blockIdx.x] = x;
   }
 }
 
-// Deterministic reduction of the per-block partial totals.  acc holds the
-// running sums over the steps of a call of entries 2..6 (reset when
-// reset != 0); out receives the totals when non-null.
-__global__ __launch_bounds__(kBlock) void k_totals(const double *partials, int nblocks,
-                                                   double *acc, int reset, double *out) {
-  __shared__ double red[kBlock];
-  __shared__ double res[kNtot];
-  for (int k = 0; k < kNtot; ++k) {
-    double x = (k == 10) ? 1.0e300 : (k == 11) ? 0.0 : 0.0;
-    for (int b = threadIdx.x; b < nblocks; b += kBlock) {
-      const double y = partials[(size_t)b * kNtot + k];
-      x = (k == 10) ? fmin(x, y) : (k == 11) ? fmax(x, y) : x + y;
+// Deterministic reduction of the per-block partial totals [kNtot][nb] by
+// one block of any size that is a multiple of 64 (up to 1024 threads).  The
+// rows are dealt to kVLanes virtual lanes (row b to lane b % kVLanes); each
+// virtual lane adds its rows in order, each virtual wave of 64 lanes is
+// reduced by the same shuffle tree, and the kVLanes / 64 wave results are
+// added in order, so the result does not depend on the block size.  acc
+// holds the running sums over the steps of a call of entries 2..6 and the
+// running maximum of entry 11 (reset when reset != 0); out receives the
+// totals when non-null.  red: kNtot * (kVLanes / 64) doubles of LDS.
+constexpr int kVLanes = 1024;
+constexpr int kVWaves = kVLanes / 64;
+
+__device__ __forceinline__ double tot_op(int k, double x, double y) {
+  return k == 10 ? fmin(x, y) : k == 11 ? fmax(x, y) : x + y;
+}
+__device__ __forceinline__ double tot_init(int k) { return k == 10 ? 1.0e300 : 0.0; }
+
+__device__ __forceinline__ void totals_reduce(const double *partials, int nb, double *acc,
+                                              int reset, double *out, double *red) {
+  const int lane = threadIdx.x & 63;
+  for (int vw = threadIdx.x >> 6; vw < kVWaves; vw += blockDim.x >> 6) {
+    const int vl = vw * 64 + lane;
+    double x[kNtot];
+#pragma unroll
+    for (int k = 0; k < kNtot; ++k) x[k] = tot_init(k);
+    for (int b = vl; b < nb; b += kVLanes) {
+#pragma unroll
+      for (int k = 0; k < kNtot; ++k) x[k] = tot_op(k, x[k], partials[(size_t)k * nb + b]);
     }
-    red[threadIdx.x] = x;
-    __syncthreads();
-    for (int s = kBlock / 2; s > 0; s >>= 1) {
-      if (threadIdx.x < s) {
-        const double y = red[threadIdx.x + s];
-        red[threadIdx.x] = (k == 10)   ? fmin(red[threadIdx.x], y)
-                           : (k == 11) ? fmax(red[threadIdx.x], y)
-                                       : red[threadIdx.x] + y;
-      }
-      __syncthreads();
+#pragma unroll
+    for (int k = 0; k < kNtot; ++k) {
+      const double y = k == 10 ? wave_min(x[k]) : k == 11 ? wave_max(x[k]) : wave_sum(x[k]);
+      if (lane == 0) red[k * kVWaves + vw] = y;
     }
-    if (threadIdx.x == 0) res[k] = red[0];
-    __syncthreads();
   }
-  if (threadIdx.x == 0) {
-    for (int k = 2; k <= 6; ++k) {
-      acc[k] = (reset ? 0.0 : acc[k]) + res[k];
-      res[k] = acc[k];
+  __syncthreads();
+  if (threadIdx.x < kNtot) {
+    const int k = threadIdx.x;
+    double x = red[k * kVWaves];
+    for (int q = 1; q < kVWaves; ++q) x = tot_op(k, x, red[k * kVWaves + q]);
+    if (k >= 2 && k <= 6) {
+      x = (reset ? 0.0 : acc[k]) + x;
+      acc[k] = x;
+    } else if (k == 11) {
+      x = reset ? x : fmax(acc[k], x);
+      acc[k] = x;
     }
-    acc[11] = reset ? res[11] : fmax(acc[11], res[11]);
-    res[11] = acc[11];
-    if (out)
-      for (int k = 0; k < kNtot; ++k) out[k] = res[k];
+    if (out) out[k] = x;
   }
+  __syncthreads();
 }
 
 }  // namespace rtk

@@ -1,9 +1,10 @@
 // Fused step kernel with the waves of a block sharing cells (angle-major
 // layout I[m][c]).
 //
-// A block holds 64 consecutive cells (one per lane) and G = ceil(nang/KA)
-// waves; wave g owns the angles m = g*KA ... g*KA + KA - 1.  Within a wave
-// the angle is uniform, so the direction cosines, weights and the upwind
+// A block holds 64 consecutive cells (one per lane) and G <= 8 waves; the
+// angles are cut into groups of KA, and wave g owns the groups g, g + G, ...
+// (NG of them at most, so up to NG*G*KA angles).  Within a wave the angle is
+// uniform, so the direction cosines, weights and the upwind
 // direction of every axis are scalars, and every intensity load reads 64
 // consecutive cells of one angle plane.  Per step:
 //   phase A  transport increment of the wave's angles (Section 4.2), one
@@ -23,11 +24,11 @@
 #include <stdint.h>
 
 #include "rt_common.hpp"
+#include "rt_internal.hpp"
 
 namespace rtk {
 
 constexpr int kNsum = 22;        // per-cell sums of phase B
-constexpr int kMaxWaves = 8;     // waves per block of the wave-group kernel
 constexpr int kChunk = 11;       // values reduced per LDS round
 
 // Reciprocal from the hardware estimate refined by Newton steps (two in
@@ -51,35 +52,6 @@ __device__ __forceinline__ A vl_face(A up2, A up1, A dn1, A h) {
   const A ab = a * b;
   const A q = (ab + ab) * fast_rcp(a + b);
   return up1 + h * (ab > A(0) ? q : A(0));
-}
-
-// Interface table and IV basis (once per call).  faces[(d*3 + j)*ncell + c]
-// for the face between the cell below c along axis d (wrapped; the edge cell
-// itself at a non-periodic low boundary, whose ghost copies it) and c:
-// j = 0 alpha, 1 hv = (1 - |u| dt/dx)/2, 2 u.  wv = 3 v E/(4pi) of the
-// current moments into mom[10..12].
-__global__ __launch_bounds__(kBlock) void k_faces(StepArgs p, double *faces, double *mom) {
-  const int c = blockIdx.x * kBlock + threadIdx.x;
-  if (c >= p.ncell) return;
-  const size_t N = (size_t)p.ncell;
-  const double sig_c = p.sa[c] + p.ss[c];
-  const int q[3] = {c % p.n[0], (c / p.n[0]) % p.n[1], c / (p.n[0] * p.n[1])};
-  for (int d = 0; d < p.ndim; ++d) {
-    int cl;
-    if (q[d] > 0)
-      cl = c - p.stride[d];
-    else if (p.bc[d][0] == kPeriodic)
-      cl = c + (p.n[d] - 1) * p.stride[d];
-    else
-      cl = c;
-    const double sig = 0.5 * ((p.sa[cl] + p.ss[cl]) + sig_c);
-    const double u = 0.5 * (p.v[(size_t)d * N + cl] + p.v[(size_t)d * N + c]);
-    faces[(size_t)(d * 3 + 0) * N + c] = alpha_of(sig, p.dl10[d]);
-    faces[(size_t)(d * 3 + 1) * N + c] = 0.5 * (1.0 - fabs(u) * p.dt_dx[d]);
-    faces[(size_t)(d * 3 + 2) * N + c] = u;
-  }
-  const double J = mom[c] * (1.0 / kFourPi);
-  for (int k = 0; k < 3; ++k) mom[(size_t)(10 + k) * N + c] = 3.0 * p.v[(size_t)k * N + c] * J;
 }
 
 // Stencil of one cell along one axis.
@@ -145,58 +117,76 @@ __device__ __forceinline__ A plane_load(const StepArgs &p, const S *Im, int idx,
 }
 
 // Sum (or, for the last value when MINLAST, minimum) of NV values over the
-// G waves of the block, lane by lane, in a fixed order; every wave receives
-// the totals.
-template <int NV, bool MINLAST>
+// G waves of the block, lane by lane, in a fixed order, R values per LDS
+// round; every wave receives the totals.  The rounds only bound the LDS
+// footprint (buf: G*R*64, tot: R*64 doubles): the result is the same for
+// every R.
+template <int NV, bool MINLAST, int R>
 __device__ __forceinline__ void waves_reduce(double (&x)[NV], double *buf, double *tot, int g,
                                              int G, int lane) {
-  static_assert(NV <= kChunk, "chunk too large");
 #pragma unroll
-  for (int v = 0; v < NV; ++v) buf[(g * NV + v) * 64 + lane] = x[v];
-  __syncthreads();
-  for (int v = g; v < NV; v += G) {
-    double s = buf[v * 64 + lane];
-    for (int j = 1; j < G; ++j) {
-      const double y = buf[(j * NV + v) * 64 + lane];
-      s = (MINLAST && v == NV - 1) ? fmin(s, y) : s + y;
+  for (int r0 = 0; r0 < NV; r0 += R) {
+    const int nr = NV - r0 < R ? NV - r0 : R;
+#pragma unroll
+    for (int v = 0; v < R; ++v)
+      if (v < nr) buf[(g * R + v) * 64 + lane] = x[r0 + v];
+    __syncthreads();
+    for (int v = g; v < nr; v += G) {
+      double s = buf[v * 64 + lane];
+      const bool mn = MINLAST && r0 + v == NV - 1;
+      for (int j = 1; j < G; ++j) {
+        const double y = buf[(j * R + v) * 64 + lane];
+        s = mn ? fmin(s, y) : s + y;
+      }
+      tot[v * 64 + lane] = s;
     }
-    tot[v * 64 + lane] = s;
-  }
-  __syncthreads();
+    __syncthreads();
 #pragma unroll
-  for (int v = 0; v < NV; ++v) x[v] = tot[v * 64 + lane];
+    for (int v = 0; v < R; ++v)
+      if (v < nr) x[r0 + v] = tot[v * 64 + lane];
+  }
 }
 
-template <typename S, typename A, int KA, bool PER, bool FUSED>
-__global__ __launch_bounds__(64 * kMaxWaves) void k_step3(StepArgs p) {
-  __shared__ double sbuf[kMaxWaves * kChunk * 64];
-  __shared__ double stot[kChunk * 64];
-  __shared__ double ssol[6 * 64];
+// Shared memory of one step body.
+// Values per reduction round: all 11 at once (the registers, not the LDS,
+// bound the blocks per CU of both storage types).
+template <typename S>
+struct Step3Smem {
+  static constexpr int R = kChunk;
+  double buf[kMaxWaves * R * 64];
+  double tot[R * 64];
+  double sol[6 * 64];
+};
+
+// One step for the 64 cells of tile blk (cells blk*64 + lane), G waves.
+// Writes I^{n+1}, the moments and the outputs of those cells and the tile's
+// partial totals into row blk of p.partials.
+template <typename S, typename A, int KA, int NG, bool PER, bool FUSED>
+__device__ __forceinline__ void step3_tile(const StepArgs &p, int blk, int G, Step3Smem<S> &sm_) {
+  constexpr int NS = KA * NG;  // angle slots of a wave: slot j*KA + k
+  double *sbuf = sm_.buf, *stot = sm_.tot, *ssol = sm_.sol;
   const int lane = threadIdx.x & 63;
   const int g = threadIdx.x >> 6;
-  const int G = blockDim.x >> 6;
-  // FP32 storage runs two blocks per CU and gains from XCD-contiguous work;
-  // the FP64 kernel (one block per CU) measured faster in dispatch order.
-  const int blk = sizeof(S) == 4 ? xcd_block(blockIdx.x, gridDim.x) : (int)blockIdx.x;
   const int c0 = blk * 64 + lane;
   const bool act = c0 < p.ncell;
   const int c = act ? c0 : p.ncell - 1;  // idle lanes shadow the last cell
   const int NA = p.nang;
-  const int m0 = g * KA;
-  const int KG = min(KA, NA - m0);  // angles of this wave (uniform, >= 1)
   const size_t N = (size_t)p.ncell;
   const S *Iin = static_cast<const S *>(p.I_in);
   S *Iout = static_cast<S *>(p.I_out);
   const double C = p.C, P = p.P, dt = p.dt;
   const double sa = p.sa[c], ss = p.ss[c], rho = p.rho[c], Tn = p.T[c];
   const double v0 = p.v[c], v1 = p.v[N + c], v2 = p.v[2 * N + c];
+  // angle of a slot (wave-uniform); valid when < NA, table reads clamped
+  auto slot_m = [&](int s) { return (g + (s / KA) * G) * KA + (s % KA); };
 
   // ------------------------------------------------ phase A: transport
-  A Ic[KA], dF[KA];
+  A Ic[NS], dF[NS];
 #pragma unroll
-  for (int k = 0; k < KA; ++k) {
-    Ic[k] = k < KG ? A(Iin[(size_t)(m0 + k) * N + c]) : A(0);
-    dF[k] = A(0);
+  for (int s = 0; s < NS; ++s) {
+    const int m = slot_m(s);
+    Ic[s] = m < NA ? A(Iin[(size_t)m * N + c]) : A(0);
+    dF[s] = A(0);
   }
   if (FUSED) {
     const int q[3] = {c % p.n[0], (c / p.n[0]) % p.n[1], c / (p.n[0] * p.n[1])};
@@ -211,13 +201,14 @@ __global__ __launch_bounds__(64 * kMaxWaves) void k_step3(StepArgs p) {
       const A dtdx = A(p.dt_dx[d]);
       const bool posR = s.uR > 0.0, posL = s.uL > 0.0;
       const bool zeroR = s.uR == 0.0, zeroL = s.uL == 0.0;
-      constexpr int UNR = sizeof(A) == 8 ? KA : 1;
+      constexpr int UNR = sizeof(A) == 8 ? NS : 1;
 #pragma unroll UNR
-      for (int k = 0; k < KA; ++k) {
-          const int m = m0 + k;
-          const A n0 = A(p.mu[m]), n1 = A(p.mu[NA + m]), n2 = A(p.mu[2 * NA + m]);
+      for (int k = 0; k < NS; ++k) {
+          const int m = slot_m(k);
+          const int mc = m < NA ? m : NA - 1;
+          const A n0 = A(p.mu[mc]), n1 = A(p.mu[NA + mc]), n2 = A(p.mu[2 * NA + mc]);
           const A mud = d == 0 ? n0 : d == 1 ? n1 : n2;
-          if (k < KG && mud != A(0)) {  // uniform over the wave
+          if (m < NA && mud != A(0)) {  // uniform over the wave
           const S *Im = Iin + (size_t)m * N;
           A IV[4];
 #pragma unroll
@@ -262,8 +253,10 @@ __global__ __launch_bounds__(64 * kMaxWaves) void k_step3(StepArgs p) {
     const S *dFin = static_cast<const S *>(p.dF_in);
     if (dFin) {
 #pragma unroll
-      for (int k = 0; k < KA; ++k)
-        if (k < KG) dF[k] = A(dFin[(size_t)(m0 + k) * N + c]);
+      for (int k = 0; k < NS; ++k) {
+        const int m = slot_m(k);
+        if (m < NA) dF[k] = A(dFin[(size_t)m * N + c]);
+      }
     }
   }
 
@@ -287,15 +280,15 @@ __global__ __launch_bounds__(64 * kMaxWaves) void k_step3(StepArgs p) {
   const A dsa = A(dt * sa), dss = A(dt * ss);
   const A D0 = A(1.0 + dt * sa * C), E0 = A(dt * sa * C), AW0 = A(1.0 + dt * C * ss);
   const A B0 = A(-dt * C * ss - dt * ss * uu / C), dssC = A(dt * ss / C);
-  A pk[KA];
+  A pk[NS];
   A sm[kNsum];
 #pragma unroll
   for (int r = 0; r < kNsum; ++r) sm[r] = A(0);
 #pragma unroll
-  for (int k = 0; k < KA; ++k) {
+  for (int k = 0; k < NS; ++k) {
     pk[k] = A(0);
-    if (k >= KG) continue;
-    const int m = m0 + k;
+    const int m = slot_m(k);
+    if (m >= NA) continue;
     const A n0 = A(p.mu[m]), n1 = A(p.mu[NA + m]), n2 = A(p.mu[2 * NA + m]);
     const A Wm = A(p.w[m]);
     const A t = n0 * Au0 + n1 * Au1 + n2 * Au2;
@@ -340,8 +333,8 @@ __global__ __launch_bounds__(64 * kMaxWaves) void k_step3(StepArgs p) {
     Sa[r] = double(sm[r]);
     Sb[r] = double(sm[kChunk + r]);
   }
-  waves_reduce<kChunk, false>(Sa, sbuf, stot, g, G, lane);
-  waves_reduce<kChunk, false>(Sb, sbuf, stot, g, G, lane);
+  waves_reduce<kChunk, false, Step3Smem<S>::R>(Sa, sbuf, stot, g, G, lane);
+  waves_reduce<kChunk, false, Step3Smem<S>::R>(Sb, sbuf, stot, g, G, lane);
   // Sa = sums 0..10, Sb = sums 11..21
 
   // --------------------------------------------- solve (FP64, wave 0)
@@ -395,9 +388,9 @@ __global__ __launch_bounds__(64 * kMaxWaves) void k_step3(StepArgs p) {
   for (int r = 0; r < 10; ++r) mo[r] = 0.0;
   mo[10] = 1.0e300;
 #pragma unroll
-  for (int k = 0; k < KA; ++k) {
-    if (k >= KG) continue;
-    const int m = m0 + k;
+  for (int k = 0; k < NS; ++k) {
+    const int m = slot_m(k);
+    if (m >= NA) continue;
     const double d0 = p.mu[m], d1 = p.mu[NA + m], d2 = p.mu[2 * NA + m];
     const A t = A(d0) * Au0 + A(d1) * Au1 + A(d2) * Au2;
     const A D = D0 - dsa * t, aw = AW0 - dss * t;
@@ -420,7 +413,7 @@ __global__ __launch_bounds__(64 * kMaxWaves) void k_step3(StepArgs p) {
     mo[9] += d1 * d2 * Iw;
     mo[10] = fmin(mo[10], double(Inew));
   }
-  waves_reduce<kChunk, true>(mo, sbuf, stot, g, G, lane);
+  waves_reduce<kChunk, true, Step3Smem<S>::R>(mo, sbuf, stot, g, G, lane);
 #pragma unroll
   for (int r = 0; r < 10; ++r) mo[r] *= kFourPi;
 
@@ -493,8 +486,53 @@ __global__ __launch_bounds__(64 * kMaxWaves) void k_step3(StepArgs p) {
 #pragma unroll
     for (int k = 0; k < kNtot; ++k) {
       const double x = (k == 10) ? wave_min(tot[k]) : (k == 11) ? wave_max(tot[k]) : wave_sum(tot[k]);
-      if (lane == 0) p.partials[(size_t)blk * kNtot + k] = x;
+      if (lane == 0) p.partials[(size_t)k * p.nparts + blk] = x;
     }
+  }
+}
+
+template <typename S, typename A, int KA, int NG, bool PER, bool FUSED>
+__global__ __launch_bounds__(64 * kMaxWaves) void k_step3(StepArgs p) {
+  __shared__ Step3Smem<S> sm_;
+  // FP32 storage runs two blocks per CU and gains from XCD-contiguous work;
+  // the FP64 kernel (one block per CU) measured faster in dispatch order.
+  const int blk = sizeof(S) == 4 ? xcd_block(blockIdx.x, gridDim.x) : (int)blockIdx.x;
+  step3_tile<S, A, KA, NG, PER, FUSED>(p, blk, blockDim.x >> 6, sm_);
+}
+
+// A whole solve per workgroup: job blockIdx.x advances its grid through
+// nsteps fused steps, tile by tile (64 cells per tile, kMaxWaves waves, the
+// same step body as k_step3, hence the same per-cell results), with the
+// totals of every step reduced like k_totals.  Between steps the workgroup
+// fences its global writes (I, moments, T) before any wave reads them.
+template <typename S, typename A, int KA, int NG, bool PER>
+__global__ __launch_bounds__(64 * kMaxWaves) void k_step3_packed(
+    const PackedJob *__restrict__ jobs) {
+  __shared__ Step3Smem<S> sm_;
+  __shared__ double red[kNtot * kVWaves];
+  const PackedJob &J = jobs[blockIdx.x];
+  StepArgs p = J.a;
+  const int ntiles = p.nparts;
+  void *Ib[2] = {const_cast<void *>(p.I_in), p.I_out};
+  double *Mb[2] = {const_cast<double *>(p.mom_in), p.mom_out};
+  double *oE = p.oE, *oF = p.oF, *oP = p.oP;
+  for (int s = 0; s < J.nsteps; ++s) {
+    const bool last = s == J.nsteps - 1;
+    p.I_in = Ib[s & 1];
+    p.I_out = Ib[(s + 1) & 1];
+    p.mom_in = Mb[s & 1];
+    p.mom_out = Mb[(s + 1) & 1];
+    p.accumulate = s > 0 ? 1 : 0;
+    p.oE = last ? oE : nullptr;
+    p.oF = last ? oF : nullptr;
+    p.oP = last ? oP : nullptr;
+    for (int t = 0; t < ntiles; ++t)
+      step3_tile<S, A, KA, NG, PER, true>(p, t, kMaxWaves, sm_);
+    __threadfence();
+    __syncthreads();
+    totals_reduce(p.partials, ntiles, J.acc, s == 0 ? 1 : 0, last ? J.totals : nullptr, red);
+    __threadfence();
+    __syncthreads();
   }
 }
 

@@ -1,4 +1,5 @@
-"""ctypes binding of the C ABI in ``include/rt.h`` (argument marshalling only).
+"""ctypes binding of the C ABI in ``include/rt.h`` and ``include/rt_serve.h``
+(argument marshalling only).
 
 Every function here has the name of the C entry point it calls.  Device
 arrays are passed as raw pointers (``int``), e.g. ``tensor.data_ptr()`` of a
@@ -17,6 +18,7 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "librt.so")
 
+RT_PENDING = 1
 RT_OK, RT_EINVAL, RT_ENOMEM, RT_EDEVICE, RT_ECFL, RT_ENOCONV, RT_EBADQUAD, RT_ESTATE, \
     RT_EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6, -7, -8
 RT_BC_PERIODIC, RT_BC_FIXED, RT_BC_COPY, RT_BC_VACUUM = 0, 1, 2, 3
@@ -64,6 +66,35 @@ class rt_info(ct.Structure):
                 ("block_threads", ct.c_int), ("grid_blocks", ct.c_longlong)]
 
 
+class rt_serve_config(ct.Structure):
+    _fields_ = [("pool_bytes", ct.c_ulonglong), ("max_active", ct.c_int),
+                ("packed_cells", ct.c_longlong), ("chunk_work", ct.c_longlong),
+                ("large_work", ct.c_longlong)]
+
+
+class rt_request(ct.Structure):
+    _fields_ = [("grid", rt_grid), ("angles", rt_angles), ("params", rt_params),
+                ("dt", ct.c_double), ("nsteps", ct.c_int), ("ghost", ct.c_void_p),
+                ("sigma_a", ct.c_void_p), ("sigma_s", ct.c_void_p), ("rho", ct.c_void_p),
+                ("T", ct.c_void_p), ("v", ct.c_void_p), ("I0", ct.c_void_p),
+                ("T_out", ct.c_void_p), ("Er", ct.c_void_p), ("Fr", ct.c_void_p),
+                ("totals", ct.c_void_p), ("I_out", ct.c_void_p)]
+
+
+class rt_serve_result(ct.Structure):
+    _fields_ = [("status", ct.c_int), ("packed", ct.c_int), ("t_submit", ct.c_double),
+                ("t_admit", ct.c_double), ("t_done", ct.c_double)]
+
+
+class rt_serve_counters(ct.Structure):
+    _fields_ = [("submitted", ct.c_longlong), ("completed", ct.c_longlong),
+                ("active", ct.c_longlong), ("peak_active", ct.c_longlong),
+                ("pool_bytes", ct.c_ulonglong), ("pool_used", ct.c_ulonglong),
+                ("peak_pool_used", ct.c_ulonglong), ("packed_launches", ct.c_longlong),
+                ("packed_requests", ct.c_longlong), ("chunk_launches", ct.c_longlong),
+                ("cell_angle_updates", ct.c_double)]
+
+
 _lib = None
 
 # (name, restype, argtypes) of every exported entry point of include/rt.h
@@ -83,21 +114,42 @@ SIGNATURES = [
                                       ct.c_void_p, ct.POINTER(rt_out), ct.c_void_p]),
     ("rt_step", ct.c_int, [ct.c_void_p, ct.c_double, ct.c_int, ct.POINTER(rt_fields),
                            ct.POINTER(rt_out), ct.c_void_p]),
+    ("rt_equilibrium_intensity", ct.c_int, [ct.c_void_p, ct.c_void_p, ct.c_void_p,
+                                            ct.c_void_p]),
     ("rt_sync_status", ct.c_int, [ct.c_void_p]),
     ("rt_profile_enable", ct.c_int, [ct.c_void_p, ct.c_int]),
     ("rt_profile_read", ct.c_int, [ct.c_void_p, ct.POINTER(ct.c_double), ct.POINTER(ct.c_int)]),
     ("rt_get_info", ct.c_int, [ct.c_void_p, ct.POINTER(rt_info)]),
     ("rt_strerror", ct.c_char_p, [ct.c_int]),
+    # include/rt_serve.h
+    ("rt_serve_create", ct.c_int, [ct.POINTER(rt_serve_config), ct.POINTER(ct.c_void_p)]),
+    ("rt_serve_submit", ct.c_int, [ct.c_void_p, ct.POINTER(rt_request),
+                                   ct.POINTER(ct.c_longlong)]),
+    ("rt_serve_poll", ct.c_int, [ct.c_void_p, ct.c_longlong, ct.POINTER(rt_serve_result)]),
+    ("rt_serve_wait", ct.c_int, [ct.c_void_p, ct.c_longlong, ct.POINTER(rt_serve_result)]),
+    ("rt_serve_now", ct.c_double, [ct.c_void_p]),
+    ("rt_serve_get_counters", ct.c_int, [ct.c_void_p, ct.POINTER(rt_serve_counters)]),
+    ("rt_serve_destroy", ct.c_int, [ct.c_void_p]),
 ]
 
 
 def lib():
-    """The loaded HIP library; raises if it has not been built."""
+    """The loaded HIP library; raises if it has not been built.
+
+    torch is imported first: its ROCm build carries its own HIP runtime,
+    which the library then binds to (same soname), so that the process holds
+    one HIP runtime and torch's streams and allocations are valid handles
+    for the library.  Loading the library first would bring in the system
+    runtime, and torch would then load a second one."""
     global _lib
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"HIP library {LIB_PATH} is not built; run "
                                "paper_1403_6126_amd.build.build() first (no fallback exists)")
+        try:
+            import torch  # noqa: F401  (one HIP runtime per process, see above)
+        except ImportError:
+            pass
         L = ct.CDLL(LIB_PATH)
         for name, res, args in SIGNATURES:
             fn = getattr(L, name)
@@ -215,6 +267,11 @@ def rt_step(ctx: int, dt: float, nsteps: int, fields: rt_fields, out: rt_out | N
            "rt_step")
 
 
+def rt_equilibrium_intensity(ctx: int, T, I, stream=0) -> None:
+    _check(lib().rt_equilibrium_intensity(ct.c_void_p(ctx), _vp(T), _vp(I), ct.c_void_p(stream)),
+           "rt_equilibrium_intensity")
+
+
 def rt_sync_status(ctx: int) -> int:
     return lib().rt_sync_status(ct.c_void_p(ctx))
 
@@ -234,3 +291,46 @@ def rt_get_info(ctx: int) -> rt_info:
     info = rt_info()
     _check(lib().rt_get_info(ct.c_void_p(ctx), ct.byref(info)), "rt_get_info")
     return info
+
+
+# ----------------------------------------------------------------- serving
+def rt_serve_create(pool_bytes: int, max_active: int, packed_cells: int, chunk_work: int,
+                    large_work: int) -> int:
+    cfg = rt_serve_config(pool_bytes, max_active, packed_cells, chunk_work, large_work)
+    out = ct.c_void_p()
+    _check(lib().rt_serve_create(ct.byref(cfg), ct.byref(out)), "rt_serve_create")
+    return out.value
+
+
+def rt_serve_submit(srv: int, req: rt_request) -> int:
+    rid = ct.c_longlong()
+    _check(lib().rt_serve_submit(ct.c_void_p(srv), ct.byref(req), ct.byref(rid)),
+           "rt_serve_submit")
+    return rid.value
+
+
+def rt_serve_poll(srv: int, rid: int):
+    """None while the request is in flight, else its rt_serve_result."""
+    res = rt_serve_result()
+    st = _check(lib().rt_serve_poll(ct.c_void_p(srv), rid, ct.byref(res)), "rt_serve_poll")
+    return None if st == RT_PENDING else res
+
+
+def rt_serve_wait(srv: int, rid: int) -> rt_serve_result:
+    res = rt_serve_result()
+    _check(lib().rt_serve_wait(ct.c_void_p(srv), rid, ct.byref(res)), "rt_serve_wait")
+    return res
+
+
+def rt_serve_now(srv: int) -> float:
+    return lib().rt_serve_now(ct.c_void_p(srv))
+
+
+def rt_serve_get_counters(srv: int) -> rt_serve_counters:
+    c = rt_serve_counters()
+    _check(lib().rt_serve_get_counters(ct.c_void_p(srv), ct.byref(c)), "rt_serve_get_counters")
+    return c
+
+
+def rt_serve_destroy(srv: int) -> None:
+    _check(lib().rt_serve_destroy(ct.c_void_p(srv)), "rt_serve_destroy")

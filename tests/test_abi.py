@@ -1,5 +1,5 @@
 """Host-side checks of the C ABI (no GPU work): every symbol declared in
-include/rt.h is exported, the library's quadrature equals the oracle's,
+include/*.h is exported, the library's quadrature equals the oracle's,
 argument validation rejects bad input before touching the device, and the
 product package never reaches the oracle."""
 import ctypes as ct
@@ -16,8 +16,13 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
 def _declared():
-    txt = open(os.path.join(ROOT, "include", "rt.h")).read()
-    return sorted(set(re.findall(r"^\s*(?:int|const char \*)\s*(rt_\w+)\s*\(", txt, re.M)))
+    names = set()
+    for h in sorted(os.listdir(os.path.join(ROOT, "include"))):
+        if h.endswith(".h"):
+            txt = open(os.path.join(ROOT, "include", h)).read()
+            names |= set(re.findall(r"^\s*(?:int|double|const char \*)\s*(rt_\w+)\s*\(",
+                                    txt, re.M))
+    return sorted(names)
 
 
 def test_library_exports_every_declared_symbol():
@@ -89,9 +94,20 @@ def test_product_package_does_not_use_oracle():
     pkg = os.path.join(ROOT, "paper_1403_6126_amd")
     for dirpath, _, files in os.walk(pkg):
         for f in files:
-            if f.endswith((".py", ".hip", ".hpp", ".cpp", ".h")):
+            if f.endswith((".py", ".hip", ".hpp", ".cpp", ".h", ".inc")):
                 txt = open(os.path.join(dirpath, f)).read()
                 assert not re.search(r"^\s*(import|from)\s+oracle", txt, re.M), f
                 assert "rt_oracle" not in txt, f
     out = subprocess.run(["ldd", rt.LIB_PATH], capture_output=True, text=True).stdout
     assert "oracle" not in out
+
+
+@pytest.mark.parametrize("field,value", [("pool_bytes", 0), ("max_active", 0),
+                                         ("chunk_work", 0), ("large_work", 0),
+                                         ("packed_cells", -1)])
+def test_serve_config_validation_before_device(field, value):
+    cfg = dict(pool_bytes=1 << 30, max_active=4, packed_cells=0, chunk_work=1, large_work=1)
+    cfg[field] = value
+    with pytest.raises(rt.RTError) as ei:
+        rt.rt_serve_create(**cfg)
+    assert ei.value.status == rt.RT_EINVAL

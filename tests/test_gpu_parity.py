@@ -97,6 +97,14 @@ CASES = [
     (3, (12, 10, 9), ("ls", 4), ((W.BC_FIXED, W.BC_FIXED), (W.BC_COPY, W.BC_VACUUM),
                                  (W.BC_PERIODIC, W.BC_PERIODIC))),
     (1, (129,), ("gl", 32), ((W.BC_VACUUM, W.BC_COPY), (0, 0), (0, 0))),
+    # more than 80 directions: 2, 3 and 4 angle groups per wave
+    (3, (9, 8, 7), ("ls", 10), None),
+    (2, (13, 11), ("ls", 12), ((W.BC_FIXED, W.BC_VACUUM), (W.BC_COPY, W.BC_FIXED), (0, 0))),
+    (3, (7, 6, 9), ("ls", 16), ((W.BC_PERIODIC, W.BC_PERIODIC), (W.BC_FIXED, W.BC_COPY),
+                                (W.BC_VACUUM, W.BC_VACUUM))),
+    (1, (150,), ("gl", 100), None),
+    # beyond 320 directions: the thread-per-cell kernel
+    (1, (70,), ("gl", 330), ((W.BC_VACUUM, W.BC_FIXED), (0, 0), (0, 0))),
 ]
 
 
@@ -204,7 +212,8 @@ def test_cfl_violation_is_rejected():
     s.close()
 
 
-@pytest.mark.parametrize("ndim,shape,quad", [(1, (512,), ("gl", 16)), (3, (18, 14, 11), ("ls", 8))])
+@pytest.mark.parametrize("ndim,shape,quad", [(1, (512,), ("gl", 16)), (3, (18, 14, 11), ("ls", 8)),
+                                             (3, (11, 9, 8), ("ls", 16))])
 def test_mixed_precision_within_1e5(ndim, shape, quad):
     import oracle
     if ndim == 1:

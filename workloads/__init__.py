@@ -19,6 +19,6 @@ Conventions (shared by both consumers):
 """
 from .configs import (  # noqa: F401
     BC_PERIODIC, BC_FIXED, BC_COPY, BC_VACUUM,
-    Workload, config1, config2, config3, config4_requests, config5,
+    Workload, config1, config2, config3, config4_requests, config5, request_workload,
     small_case, equilibrium_intensity, moment_intensity, lognormal,
 )

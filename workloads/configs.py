@@ -246,12 +246,17 @@ def config4_requests(count: int = 2000, seed: int = 4, min_cells: int = 64,
     return reqs
 
 
+REQUEST_DX = 1.0 / 512
+
+
 def request_workload(req: Dict, precision: str = "mixed") -> Workload:
     """Fields of one serving request: as configuration 1 (lognormal rho and T,
-    sigma_a = rho, sigma_s = 10 rho) with every velocity component uniform in
-    [-0.01, 0.01]."""
+    sigma_a = rho, sigma_s = 10 rho, cells of size 1/512, so the optical
+    depth per cell is that of configuration 1 whatever the grid) with every
+    velocity component uniform in [-0.01, 0.01]."""
     ndim = req["ndim"]
-    n, dx = _grid(ndim, req["shape"])
+    shape = tuple(req["shape"])
+    n, dx = _grid(ndim, shape, box=tuple(s * REQUEST_DX for s in shape) + (1.0,) * (3 - ndim))
     nc = n[0] * n[1] * n[2]
     rng = np.random.Generator(np.random.PCG64(req["seed"]))
     rho = lognormal(rng, 0.5, nc)
