@@ -114,6 +114,56 @@ def cpu_baseline(wl, budget_s: float = 12.0, batch: int = 65536, seed: int = 0):
                        f"{el:.1f} s")
 
 
+SERVE_DEFAULTS = dict(pool_bytes=96 << 30, max_active=1024, packed_cells=4096,
+                      chunk_work=400_000_000, large_work=40_000_000)
+
+
+def serving(count: int, load: float, warm: int, seed: int = 4, fifo: bool = True):
+    """The serving stream: `count` requests of the mixed-size trace (1D/2D/3D
+    grids of 64 to 128^3 cells log-uniform, 16-288 directions, 10-200 steps,
+    FP32-mixed, Poisson arrivals).  The batched capacity is measured first in
+    a closed loop over the first `warm` requests; arrivals are then scaled so
+    that the offered load is `load` times that capacity, and the same trace
+    runs through the server and through the plain one-at-a-time path."""
+    import numpy as np
+    import torch
+
+    import workloads as W
+    from paper_1403_6126_amd import serve
+
+    def say(msg):
+        print(f"bench: serving {msg}", file=sys.stderr, flush=True)
+
+    reqs = W.config4_requests(count, seed=seed)
+    wls = [W.request_workload(r, precision="mixed") for r in reqs]
+    work = np.array([wl.ncell * wl.nsteps * _nang(r["quad"]) for wl, r in zip(wls, reqs)],
+                    dtype=np.float64)
+    say(f"{count} requests generated")
+    cap = serve.run_batched(wls[:warm], [0.0] * warm, progress=say, **SERVE_DEFAULTS)
+    rate = load * cap["throughput"] / work.mean()          # requests per second
+    arrivals = np.cumsum([r["gap"] for r in reqs]) / rate
+    arrivals -= arrivals[0]
+    print(f"bench: serving capacity {cap['throughput']:.3g} updates/s, offered "
+          f"{rate:.3g} req/s over {arrivals[-1]:.1f} s", file=sys.stderr, flush=True)
+    b = serve.run_batched(wls, arrivals, progress=say, **SERVE_DEFAULTS)
+    print(f"bench: served p50 {b['latency_p50_s']*1e3:.1f} ms p99 {b['latency_p99_s']*1e3:.1f} ms "
+          f"{b['throughput']:.3g} updates/s", file=sys.stderr, flush=True)
+    torch.cuda.empty_cache()
+    f = None
+    if fifo:
+        f = serve.run_fifo(wls, arrivals, progress=say)
+        print(f"bench: fifo p50 {f['latency_p50_s']*1e3:.1f} ms p99 {f['latency_p99_s']*1e3:.1f} ms "
+              f"{f['throughput']:.3g} updates/s", file=sys.stderr, flush=True)
+    return dict(requests=count, load=load, closed_loop_capacity=cap["throughput"],
+                offered_req_per_s=rate, mean_updates_per_request=float(work.mean()),
+                batched=b, fifo=f, server=SERVE_DEFAULTS,
+                latency="submission to results in host memory")
+
+
+def _nang(quad):
+    return quad[1] if quad[0] == "gl" else quad[1] * (quad[1] + 2)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -125,6 +175,11 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=12.0)
     ap.add_argument("--only", choices=["fp64", "mixed"], default=None,
                     help="profiling: run one precision only and print its timing")
+    ap.add_argument("--serve-requests", type=int, default=200,
+                    help="requests of the serving trace (0: skip; 2000 = the full stream)")
+    ap.add_argument("--serve-load", type=float, default=0.8)
+    ap.add_argument("--serve-warm", type=int, default=50)
+    ap.add_argument("--only-serve", action="store_true")
     ap.add_argument("--copy-probe", type=float, default=0.0,
                     help="profiling: time a plain device-to-device copy of this many GiB "
                          "(counter calibration) and exit")
@@ -148,6 +203,10 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         print(json.dumps({"copy_probe_bytes_each_way": 8 * n, "launches": args.steps}))
+        return
+    if args.only_serve:
+        print(json.dumps(serving(args.serve_requests, args.serve_load, args.serve_warm)),
+              flush=True)
         return
     wl = W.config2(nper=args.nper)
     wname = f"box3d_{args.nper}cube_S8"
@@ -174,6 +233,11 @@ def main():
                                    kernel="rtk::k_step3<float, float, 10, true, true>",
                                    kernel_ms=rmx["kernel_ms"],
                                    bytes_per_launch=rmx["bytes_per_launch"]))
+    srv = None
+    if args.serve_requests > 0:
+        import torch
+        torch.cuda.empty_cache()
+        srv = serving(args.serve_requests, args.serve_load, args.serve_warm)
     cpu = None
     if not args.no_cpu_baseline:
         print("bench: cpu baseline (oracle)", file=sys.stderr, flush=True)
@@ -202,6 +266,7 @@ def main():
                      "kernel": "rtk::k_step3<double, double, 10, true, true>",
                      "kernel_ms": r64["kernel_ms"], "bytes_per_launch": r64["bytes_per_launch"]},
         "fp32_mixed": mixed,
+        "serving": srv,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)

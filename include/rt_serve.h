@@ -21,10 +21,11 @@
  *     requests of at most packed_cells cells are packed into persistent
  *     launches in which one workgroup advances a whole solve; every other
  *     request advances by chunks of about chunk_work cell-angle updates,
- *     at most two chunks in flight per request, on one of two streams (one
- *     for requests of at least large_work updates per step, one for the
- *     rest), so that requests arriving while others run start at once and
- *     their work overlaps on the device;
+ *     at most two chunks in flight per request, on one of two streams: the
+ *     requests of at least large_work updates per step run one at a time in
+ *     submission order on the first, the others round-robin on the second,
+ *     so that requests arriving while others run start at once and their
+ *     work overlaps the large request on the device;
  *   - on completion the IO thread copies the results to the caller's host
  *     buffers and releases the arena memory.
  * A request's results do not depend on the other requests in flight: each

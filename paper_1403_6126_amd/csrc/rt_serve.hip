@@ -432,7 +432,16 @@ void rt_server::sched_loop() {
       batches.push_back(std::move(b));
       progress = true;
     }
-    // chunked requests: keep up to two chunks in flight each
+    // chunked requests: keep up to two chunks in flight each.  Large
+    // requests go one at a time in submission order (the oldest unfinished
+    // one issues), the others round-robin, so that small and medium work
+    // overlaps the large request on the device instead of queueing behind it
+    // and the large ones keep their stand-alone service time.
+    long long large_head = -1;
+    for (Request *q : running)
+      if (q->large && q->steps_issued < q->r.nsteps && q->status == RT_OK &&
+          (large_head < 0 || q->id < large_head))
+        large_head = q->id;
     std::vector<Request *> finished;
     for (size_t i = 0; i < running.size();) {
       Request *q = running[i];
@@ -449,7 +458,7 @@ void rt_server::sched_loop() {
           running.pop_back();
           continue;
         }
-      } else if (q->n_inflight < 2) {
+      } else if (q->n_inflight < 2 && (!q->large || q->id == large_head)) {
         hipStream_t s = q->large ? s_large : s_small;
         if (q->steps_issued == 0) hipStreamWaitEvent(s, q->ev_ready, 0);
         const int k0 = q->steps_issued, k1 = std::min(nsteps, k0 + q->chunk);

@@ -128,7 +128,7 @@ def _percentiles(lat: Sequence[float]) -> Dict[str, float]:
                 mean=float(x.mean()), max=float(x.max()))
 
 
-def run_batched(wls: List, arrivals: Sequence[float], **server_kw) -> Dict:
+def run_batched(wls: List, arrivals: Sequence[float], progress=None, **server_kw) -> Dict:
     """Replays the trace against the server: request i is submitted at
     arrivals[i] seconds after the start; returns latencies (submission to
     results in host memory) and aggregate throughput."""
@@ -140,7 +140,13 @@ def run_batched(wls: List, arrivals: Sequence[float], **server_kw) -> Dict:
             if delay > 0:
                 time.sleep(delay)
             handles[i] = s.submit(wl)
-        res = [s.wait(h) for h in handles]
+            if progress and (i + 1) % 50 == 0:
+                progress(f"submitted {i + 1}/{len(wls)}")
+        res = []
+        for i, h in enumerate(handles):
+            res.append(s.wait(h))
+            if progress and (i + 1) % 50 == 0:
+                progress(f"completed {i + 1}/{len(wls)}")
         counters = s.counters()
     bad = [r["status"] for r in res if r["status"] != rt.RT_OK]
     if bad:
@@ -159,7 +165,7 @@ def run_batched(wls: List, arrivals: Sequence[float], **server_kw) -> Dict:
     return out
 
 
-def run_fifo(wls: List, arrivals: Sequence[float]) -> Dict:
+def run_fifo(wls: List, arrivals: Sequence[float], progress=None) -> Dict:
     """The same trace through the plain path: one request at a time in
     arrival order, each created, uploaded, stepped with rt_step, copied back
     and destroyed before the next starts."""
@@ -203,6 +209,8 @@ def run_fifo(wls: List, arrivals: Sequence[float]) -> Dict:
         lat.append(done - arrive)
         work += float(nc) * nang * wl.nsteps
         del T_h, E_h, F_h, tot_h
+        if progress and (i + 1) % 50 == 0:
+            progress(f"plain path {i + 1}/{len(wls)}")
     out = dict(requests=len(wls), makespan_s=t_last - t_first, updates=work,
                throughput=work / (t_last - t_first))
     out.update({f"latency_{k}_s": v for k, v in _percentiles(lat).items()})

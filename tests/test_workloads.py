@@ -14,6 +14,8 @@ def test_config4_requests_are_well_posed(orc):
             continue
         wl = W.request_workload(dict(r, nsteps=min(r["nsteps"], 6)), precision="fp64")
         st = orc.run(wl, wl.nsteps)
+        # (intensities may dip below zero next to large contrasts: the centred
+        # part of the interface flux, weighted 1 - alpha, is not positive)
         assert np.all(st.T > 0) and st.newton_max <= 8, r
         done += 1
     assert done >= 10
@@ -25,6 +27,7 @@ def test_config4_request_shapes():
     assert cells.min() >= 8 and cells.max() <= 2 * 128 ** 3
     for r in reqs:
         wl = W.request_workload(dict(r, shape=(4,) * r["ndim"]), precision="mixed")
-        assert wl.dx[0] == W.configs.REQUEST_DX and wl.courant == 0.5
+        assert wl.dx[0] == W.configs.REQUEST_DX
+        assert abs(wl.courant * np.sqrt(r["ndim"]) - 0.5) < 1e-15
         nang = r["quad"][1] if r["quad"][0] == "gl" else r["quad"][1] * (r["quad"][1] + 2)
         assert 16 <= nang <= 288

@@ -264,8 +264,12 @@ def request_workload(req: Dict, precision: str = "mixed") -> Workload:
     v = np.zeros((3, nc))
     ncomp = 1 if req["quad"][0] == "gl" else 3
     v[:ncomp] = rng.uniform(-0.01, 0.01, (ncomp, nc))
+    # Courant number 0.5 along the fastest ray, as in configuration 1: the sum
+    # over the axes of |n_d| C dt / dx is at most 0.5 (|n| = 1 gives
+    # sum_d |n_d| <= sqrt(ndim)), the range in which the unsplit limited
+    # transport keeps intensities non-negative.
     w = Workload(name=f"request-{req['id']}", n=n, ndim=ndim, dx=dx,
-                 bc=_periodic(ndim), quad=req["quad"], courant=0.5,
+                 bc=_periodic(ndim), quad=req["quad"], courant=0.5 / math.sqrt(ndim),
                  nsteps=req["nsteps"], precision=precision, rho=rho, T=T, v=v,
                  sigma_a=rho.copy(), sigma_s=10.0 * rho)
     w.init = lambda mu, T=T: equilibrium_intensity(T, mu.shape[0])
