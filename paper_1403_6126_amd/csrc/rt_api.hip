@@ -44,9 +44,9 @@ __global__ __launch_bounds__(kBlock) void k_faces(StepArgs p, double *faces, dou
 }
 
 __global__ __launch_bounds__(kVLanes) void k_totals(const double *partials, int nblocks,
-                                                    double *acc, int reset, double *out) {
+                                                    double *out) {
   __shared__ double red[kNtot * kVWaves];
-  totals_reduce(partials, nblocks, acc, reset, out, red);
+  totals_reduce(partials, nblocks, out, red);
 }
 
 
@@ -172,10 +172,11 @@ int one_step(rt_ctx *c, double dt, const rt_fields *f, const void *dF, bool fuse
     hipEventRecord(e1, s);
     c->pending.emplace_back(e0, e1);
   }
-  hipLaunchKernelGGL(k_totals, dim3(1), dim3(kVLanes), 0, s, c->partials,
-                     (int)ctx_step_blocks(c), c->acc, first ? 1 : 0,
-                     (last && o) ? o->totals : nullptr);
-  if (!hip_ok(hipGetLastError())) return RT_EDEVICE;
+  if (last && o && o->totals) {
+    hipLaunchKernelGGL(k_totals, dim3(1), dim3(kVLanes), 0, s, c->partials,
+                       (int)ctx_step_blocks(c), o->totals);
+    if (!hip_ok(hipGetLastError())) return RT_EDEVICE;
+  }
   c->cur = 1 - c->cur;
   c->mom_cur = 1 - c->mom_cur;
   c->mom_valid = true;
@@ -298,7 +299,7 @@ int ctx_init_host(const rt_grid *g, const rt_angles *an, const rt_params *p, rt_
 namespace {
 // Scratch layout: offsets of the pieces in one block.
 struct Plan {
-  size_t mu, w, ghost, mom0, mom1, faces, partials, acc, status, total;
+  size_t mu, w, ghost, mom0, mom1, faces, partials, status, total;
 };
 Plan plan_of(const rt_ctx *c) {
   Plan q;
@@ -316,7 +317,6 @@ Plan plan_of(const rt_ctx *c) {
   q.mom1 = take(sizeof(double) * kNmomX * nc);
   q.faces = take(sizeof(double) * 9 * nc);
   q.partials = take(sizeof(double) * kNtot * c->nblocks);
-  q.acc = take(sizeof(double) * kNtot);
   q.status = take(sizeof(int));
   q.total = o;
   return q;
@@ -335,7 +335,6 @@ int ctx_attach_scratch(rt_ctx *c, char *base, hipStream_t s) {
   c->mom[1] = reinterpret_cast<double *>(base + q.mom1);
   c->faces = reinterpret_cast<double *>(base + q.faces);
   c->partials = reinterpret_cast<double *>(base + q.partials);
-  c->acc = reinterpret_cast<double *>(base + q.acc);
   c->status = reinterpret_cast<int *>(base + q.status);
   const bool ok =
       hip_ok(hipMemcpyAsync(c->d_mu, c->h_mu.data(), sizeof(double) * 3 * N,
@@ -344,8 +343,7 @@ int ctx_attach_scratch(rt_ctx *c, char *base, hipStream_t s) {
                             s)) &&
       hip_ok(hipMemcpyAsync(c->d_ghost, c->h_ghost.data(), sizeof(double) * 6 * N,
                             hipMemcpyHostToDevice, s)) &&
-      hip_ok(hipMemsetAsync(c->status, 0, sizeof(int), s)) &&
-      hip_ok(hipMemsetAsync(c->acc, 0, sizeof(double) * kNtot, s));
+      hip_ok(hipMemsetAsync(c->status, 0, sizeof(int), s));
   return ok ? RT_OK : RT_EDEVICE;
 }
 

@@ -94,8 +94,26 @@ __device__ __forceinline__ double wave_max(double x) {
   return x;
 }
 
+// Stores a block's totals of one step into its row b of the partials
+// [kNtot][nparts]: the exchange sums (entries 2..6) add to the row's value
+// from the earlier steps of the call, entry 11 keeps the maximum, the state
+// entries are overwritten.  accumulate = 0 on the first step of a call.
+// The rows are reduced once, after the last step of the call.
+__device__ __forceinline__ void store_partial(double *partials, int nparts, int b, int k, double x,
+                                              int accumulate) {
+  double *dst = partials + (size_t)k * nparts + b;
+  if (accumulate) {
+    if (k >= 2 && k <= 6)
+      x = *dst + x;
+    else if (k == 11)
+      x = fmax(*dst, x);
+  }
+  *dst = x;
+}
+
 // Deterministic per-block reduction of the totals vector into partials.
-__device__ __forceinline__ void block_totals(double (&t)[kNtot], double *partials, int nparts) {
+__device__ __forceinline__ void block_totals(double (&t)[kNtot], double *partials, int nparts,
+                                             int accumulate) {
   __shared__ double red[kBlock / 64][kNtot];
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
 #pragma unroll
@@ -110,7 +128,7 @@ __device__ __forceinline__ void block_totals(double (&t)[kNtot], double *partial
     double x = red[0][k];
     for (int q = 1; q < kBlock / 64; ++q)
       x = (k == 10) ? fmin(x, red[q][k]) : (k == 11) ? fmax(x, red[q][k]) : x + red[q][k];
-    partials[(size_t)k * nparts + blockIdx.x] = x;
+    store_partial(partials, nparts, blockIdx.x, k, x, accumulate);
   }
 }
 
@@ -119,10 +137,8 @@ __device__ __forceinline__ void block_totals(double (&t)[kNtot], double *partial
 // rows are dealt to kVLanes virtual lanes (row b to lane b % kVLanes); each
 // virtual lane adds its rows in order, each virtual wave of 64 lanes is
 // reduced by the same shuffle tree, and the kVLanes / 64 wave results are
-// added in order, so the result does not depend on the block size.  acc
-// holds the running sums over the steps of a call of entries 2..6 and the
-// running maximum of entry 11 (reset when reset != 0); out receives the
-// totals when non-null.  red: kNtot * (kVLanes / 64) doubles of LDS.
+// added in order, so the result does not depend on the block size.  out
+// receives the kNtot totals.  red: kNtot * (kVLanes / 64) doubles of LDS.
 constexpr int kVLanes = 1024;
 constexpr int kVWaves = kVLanes / 64;
 
@@ -131,8 +147,8 @@ __device__ __forceinline__ double tot_op(int k, double x, double y) {
 }
 __device__ __forceinline__ double tot_init(int k) { return k == 10 ? 1.0e300 : 0.0; }
 
-__device__ __forceinline__ void totals_reduce(const double *partials, int nb, double *acc,
-                                              int reset, double *out, double *red) {
+__device__ __forceinline__ void totals_reduce(const double *partials, int nb, double *out,
+                                              double *red) {
   const int lane = threadIdx.x & 63;
   for (int vw = threadIdx.x >> 6; vw < kVWaves; vw += blockDim.x >> 6) {
     const int vl = vw * 64 + lane;
@@ -154,14 +170,7 @@ __device__ __forceinline__ void totals_reduce(const double *partials, int nb, do
     const int k = threadIdx.x;
     double x = red[k * kVWaves];
     for (int q = 1; q < kVWaves; ++q) x = tot_op(k, x, red[k * kVWaves + q]);
-    if (k >= 2 && k <= 6) {
-      x = (reset ? 0.0 : acc[k]) + x;
-      acc[k] = x;
-    } else if (k == 11) {
-      x = reset ? x : fmax(acc[k], x);
-      acc[k] = x;
-    }
-    if (out) out[k] = x;
+    out[k] = x;
   }
   __syncthreads();
 }

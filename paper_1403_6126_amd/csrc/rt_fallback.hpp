@@ -414,7 +414,7 @@ __global__ __launch_bounds__(kBlock) void k_step(StepArgs p) {
     tot[10] = imin;
     tot[11] = double(it);
   }
-  block_totals(tot, p.partials, p.nparts);
+  block_totals(tot, p.partials, p.nparts, p.accumulate);
 }
 
 }  // namespace rtk

@@ -32,8 +32,7 @@ struct PackedJob {
   StepArgs a;
   int nsteps;
   int pad_;
-  double *acc;     // [kNtot] running totals
-  double *totals;  // [kNtot] totals after the last step (nullable)
+  double *totals;  // [kNtot] totals of the solve (nullable)
 };
 
 // Step launchers (defined in rt_kernels_f64.hip / rt_kernels_f32.hip).
@@ -72,8 +71,7 @@ struct rt_ctx {
   double *faces = nullptr;              // [3][3][ncell] interface table of the call
   rtk::KShape shape;
   bool mom_valid = false;
-  double *partials = nullptr;           // [kNtot][nblocks]
-  double *acc = nullptr;
+  double *partials = nullptr;           // [kNtot][nblocks], kept over the steps of a call
   int *status = nullptr;
   long long nblocks = 0;
   bool profile = false;
@@ -89,7 +87,7 @@ namespace rtk {
 // device calls).  Returns an rt_status.
 int ctx_init_host(const rt_grid *g, const rt_angles *a, const rt_params *p, rt_ctx *c);
 // Bytes of device scratch the context needs (tables, moments, interface
-// table, partial totals, running totals, status word), 256-byte aligned.
+// table, partial totals, status word), 256-byte aligned.
 size_t ctx_scratch_bytes(const rt_ctx *c);
 // Points the context's scratch into base (ctx_scratch_bytes long) and
 // uploads the tables / clears the counters on stream s.

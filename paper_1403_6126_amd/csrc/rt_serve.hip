@@ -413,7 +413,6 @@ void rt_server::sched_loop() {
         j.a.oE = q->d_E;
         j.a.oF = q->d_F;
         j.nsteps = q->r.nsteps;
-        j.acc = c.acc;
         j.totals = q->d_tot;
         hipStreamWaitEvent(s_pack, q->ev_ready, 0);
       }

@@ -486,7 +486,7 @@ __device__ __forceinline__ void step3_tile(const StepArgs &p, int blk, int G, St
 #pragma unroll
     for (int k = 0; k < kNtot; ++k) {
       const double x = (k == 10) ? wave_min(tot[k]) : (k == 11) ? wave_max(tot[k]) : wave_sum(tot[k]);
-      if (lane == 0) p.partials[(size_t)k * p.nparts + blk] = x;
+      if (lane == 0) store_partial(p.partials, p.nparts, blk, k, x, p.accumulate);
     }
   }
 }
@@ -502,9 +502,10 @@ __global__ __launch_bounds__(64 * kMaxWaves) void k_step3(StepArgs p) {
 
 // A whole solve per workgroup: job blockIdx.x advances its grid through
 // nsteps fused steps, tile by tile (64 cells per tile, kMaxWaves waves, the
-// same step body as k_step3, hence the same per-cell results), with the
-// totals of every step reduced like k_totals.  Between steps the workgroup
-// fences its global writes (I, moments, T) before any wave reads them.
+// same step body as k_step3, hence the same per-cell results and partial
+// totals), and reduces the partial totals after the last step like
+// k_totals.  Between steps the workgroup fences its global writes (I,
+// moments, T, partials) before any wave reads them.
 template <typename S, typename A, int KA, int NG, bool PER>
 __global__ __launch_bounds__(64 * kMaxWaves) void k_step3_packed(
     const PackedJob *__restrict__ jobs) {
@@ -530,10 +531,8 @@ __global__ __launch_bounds__(64 * kMaxWaves) void k_step3_packed(
       step3_tile<S, A, KA, NG, PER, true>(p, t, kMaxWaves, sm_);
     __threadfence();
     __syncthreads();
-    totals_reduce(p.partials, ntiles, J.acc, s == 0 ? 1 : 0, last ? J.totals : nullptr, red);
-    __threadfence();
-    __syncthreads();
   }
+  if (J.totals) totals_reduce(p.partials, ntiles, J.totals, red);
 }
 
 }  // namespace rtk
