@@ -166,7 +166,9 @@ __device__ __forceinline__ void step3_tile(const StepArgs &p, int blk, int G, St
   constexpr int NS = KA * NG;  // angle slots of a wave: slot j*KA + k
   double *sbuf = sm_.buf, *stot = sm_.tot, *ssol = sm_.sol;
   const int lane = threadIdx.x & 63;
-  const int g = threadIdx.x >> 6;
+  // wave index, made provably wave-uniform so that the angle of a slot, the
+  // direction cosines and the plane offsets live in scalar registers
+  const int g = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int c0 = blk * 64 + lane;
   const bool act = c0 < p.ncell;
   const int c = act ? c0 : p.ncell - 1;  // idle lanes shadow the last cell
@@ -491,8 +493,21 @@ __device__ __forceinline__ void step3_tile(const StepArgs &p, int blk, int G, St
   }
 }
 
+// Waves per SIMD the register allocation of k_step3 targets (8-wave blocks:
+// 2 = one block per CU, 4 = two, 6 = three).  Measured on the 128^3 S8 box:
+// FP64 at 4 (128 VGPRs, a small spill) runs 5.0 ms against 6.0 ms at 2;
+// FP32 at 6 (80 VGPRs) spills enough to lose to 4.
+#ifndef RT_STEP3_WAVES_F64
+#define RT_STEP3_WAVES_F64 4
+#endif
+#ifndef RT_STEP3_WAVES_F32
+#define RT_STEP3_WAVES_F32 4
+#endif
+
 template <typename S, typename A, int KA, int NG, bool PER, bool FUSED>
-__global__ __launch_bounds__(64 * kMaxWaves) void k_step3(StepArgs p) {
+__global__ __launch_bounds__(64 * kMaxWaves, sizeof(S) == 8 ? RT_STEP3_WAVES_F64
+                                                            : RT_STEP3_WAVES_F32) void
+k_step3(StepArgs p) {
   __shared__ Step3Smem<S> sm_;
   // FP32 storage runs two blocks per CU and gains from XCD-contiguous work;
   // the FP64 kernel (one block per CU) measured faster in dispatch order.
