@@ -1,0 +1,196 @@
+"""The shadow and advective-diffusion workloads on the GPU.
+
+* Shadow (Section 5.8 geometry: a collimated beam from the -x face, an
+  absorbing ellipsoidal clump of density contrast 1e3, fixed background
+  inflow elsewhere): FP32-mixed against the FP64 oracle on a 32^3 copy, and
+  at the full 256^3 against the GPU FP64 path, block-averaged to 64^3.  The
+  64^3 copy against the oracle runs when RT_LONG=1 (minutes of CPU).
+* Advective diffusion (Section 5.5 in 3D, flow held at v, no velocity
+  estimate): at 512x512x256 cells the variance of the pulse grows by 2 D t
+  per axis, D = C/(3 sigma_s), and its centroid moves by v t; a 64x64x32
+  copy matches the oracle.
+Errors are normwise, max|a - b| / max|b| per field.
+"""
+import math
+import os
+
+import numpy as np
+import pytest
+
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+TOL_MIXED = 1e-5
+
+
+def _nerr(a, b):
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
+
+
+def _device_init(wl, mu, precision):
+    """Initial intensities of the workload, filled on the device angle by
+    angle from the same seeded fields (the host array would be too large)."""
+    import torch
+    dt = torch.float32 if precision == "mixed" else torch.float64
+    nang, nc = len(mu), wl.ncell
+    I0 = torch.empty((nang, nc), dtype=dt, device="cuda")
+    if "E0" in wl.meta:  # I = (E + 3 n.F)/(4 pi)
+        E = torch.as_tensor(wl.meta["E0"], device="cuda")
+        F = torch.as_tensor(wl.meta["F0"], device="cuda")
+        for m in range(nang):
+            n = [float(x) for x in mu[m]]
+            I0[m] = (E + 3.0 * (n[0] * F[0] + n[1] * F[1] + n[2] * F[2])) / (4.0 * math.pi)
+    else:  # I = T^4/(4 pi)
+        T = torch.as_tensor(wl.T, device="cuda")
+        I0[:] = W.equilibrium_intensity(T, nang, xp=torch)
+    return I0
+
+
+def _run_gpu(wl, precision, nsteps=None, estimate_v=True):
+    import torch
+
+    from paper_1403_6126_amd.solver import Solver, quadrature_for
+    mu, w = quadrature_for(wl.quad)
+    I0 = _device_init(wl, mu, precision)
+    s = Solver(wl, precision=precision, mu=mu, w=w, I0=I0, estimate_v=estimate_v)
+    del I0
+    s.step(wl.nsteps if nsteps is None else nsteps)
+    torch.cuda.synchronize()
+    st = s.status()
+    return s, st
+
+
+def _shadow_vs_oracle(nper, nsteps):
+    import oracle
+    wl = W.config3(nper=nper, nsteps=nsteps, precision="mixed")
+    s, st = _run_gpu(wl, "mixed")
+    assert st == 0
+    got = s.state()
+    s.close()
+    ref = oracle.run(wl, nsteps)
+    errs = dict(E=_nerr(got["E"], ref.E), F=_nerr(got["F"], ref.F), T=_nerr(got["T"], ref.T),
+                I=_nerr(got["I"], ref.I))
+    tg, tr = got["totals"], ref.totals()
+    drift = abs((tg[0] + tg[1]) - (tr[0] + tr[1])) / abs(tr[0] + tr[1])
+    print(f"shadow {nper}^3 x {nsteps} steps, mixed vs oracle: {errs}, total energy {drift:.2e}",
+          flush=True)
+    return errs, drift
+
+
+def test_shadow_32_mixed_matches_oracle():
+    errs, drift = _shadow_vs_oracle(32, 50)
+    assert max(errs["E"], errs["F"], errs["T"]) <= TOL_MIXED and drift <= TOL_MIXED, errs
+
+
+@pytest.mark.skipif(os.environ.get("RT_LONG") != "1", reason="minutes of CPU oracle; RT_LONG=1")
+def test_shadow_64_mixed_matches_oracle():
+    errs, drift = _shadow_vs_oracle(64, 50)
+    assert max(errs["E"], errs["F"], errs["T"]) <= TOL_MIXED and drift <= TOL_MIXED, errs
+
+
+def _block_mean(a, n, f):
+    a = a.reshape(n, n, n)
+    return a.reshape(n // f, f, n // f, f, n // f, f).mean(axis=(1, 3, 5))
+
+
+def test_shadow_256_mixed_vs_fp64():
+    """Full size, 50 steps: the beam front has crossed the clump's near edge;
+    the FP32-mixed fields against the FP64 fields, block-averaged to 64^3."""
+    import torch
+    n = 256
+    res = {}
+    for prec in ("fp64", "mixed"):
+        wl = W.config3(nper=n, nsteps=50, precision=prec)
+        s, st = _run_gpu(wl, prec)
+        assert st == 0
+        res[prec] = dict(E=s.E.cpu().numpy(), T=s.T.cpu().numpy(),
+                         tot=s.totals.cpu().numpy())
+        s.close()
+        del s
+        torch.cuda.empty_cache()
+    a, b = res["mixed"], res["fp64"]
+    errs = dict(E64=_nerr(_block_mean(a["E"], n, 4), _block_mean(b["E"], n, 4)),
+                T64=_nerr(_block_mean(a["T"], n, 4), _block_mean(b["T"], n, 4)),
+                E=_nerr(a["E"], b["E"]), T=_nerr(a["T"], b["T"]))
+    e_a, e_b = a["tot"][0] + a["tot"][1], b["tot"][0] + b["tot"][1]
+    errs["energy"] = abs(e_a - e_b) / abs(e_b)
+    # the beam reached the clump: its near side heated above the background
+    print("shadow 256^3 mixed vs fp64:", errs, flush=True)
+    assert max(errs["E64"], errs["T64"], errs["energy"]) <= TOL_MIXED, errs
+
+
+def _pulse_stats(E, wl):
+    """Centroid and variance per axis of E minus the far-field background
+    (periodic box, pulse far from the x and y edges).  The background is the
+    mean of E over the corner columns, at least 7 widths from the pulse in x
+    and in y: every background cell evolves identically, so in FP32 they all
+    carry the same rounding drift, and over the whole box even a relative
+    1e-6 offset would weigh on the variance as much as the diffusion."""
+    import torch
+    n = wl.n
+    w = wl.meta["width"]
+    x0 = wl.meta["centre"]
+    e3 = E.reshape(n[2], n[1], n[0])
+    xs = (torch.arange(n[0], device=E.device, dtype=torch.float64) + 0.5) * wl.dx[0]
+    ys = (torch.arange(n[1], device=E.device, dtype=torch.float64) + 0.5) * wl.dx[1]
+    far = ((xs - x0[0]).abs() > 7 * w)[None, None, :] & ((ys - x0[1]).abs() > 7 * w)[None, :, None]
+    far = far.expand(n[2], n[1], n[0])
+    bg = float(e3[far].mean())
+    e = e3 - bg
+    tot = e.sum()
+    out = []
+    for d, axis in ((0, 2), (1, 1), (2, 0)):
+        x = (torch.arange(n[d], device=E.device, dtype=torch.float64) + 0.5) * wl.dx[d]
+        prof = e.sum(dim=tuple(k for k in range(3) if k != axis))
+        mean = (prof * x).sum() / tot
+        var = (prof * (x - mean) ** 2).sum() / tot
+        out.append((float(mean), float(var)))
+    return out, bg
+
+
+def test_diffusion_full_size_variance_growth():
+    """Section 5.5 in 3D, FP32-mixed: the analytic solution holds the flow at
+    v, so the step runs without the velocity estimate (with it, radiation
+    pressure on the fixed-velocity gas enters the comoving flux and the
+    variance grows faster, by half again at C = P = 1)."""
+    import torch
+    wl = W.config5(precision="mixed")
+    t = wl.nsteps * wl.dt
+    D = wl.meta["diffusion"]
+    E0 = torch.as_tensor(wl.meta["E0"], device="cuda")
+    before, bg0 = _pulse_stats(E0, wl)
+    erad0 = float(E0.sum())
+    del E0
+    s, st = _run_gpu(wl, "mixed", estimate_v=False)
+    assert st == 0
+    after, bg1 = _pulse_stats(s.E, wl)
+    erad1 = float(s.E.sum())
+    s.close()
+    del s
+    torch.cuda.empty_cache()
+    ratios = [(a[1] - b[1]) / (2 * D * t) for a, b in zip(after, before)]
+    shift = (after[0][0] - before[0][0]) / (wl.v[0][0] * t)
+    drift = abs(erad1 - erad0) / erad0
+    print(f"diffusion 512x512x256 mixed: variance growth / 2Dt per axis {ratios}, "
+          f"x centroid shift / v t {shift:.4f}, background {bg0:.9f} -> {bg1:.9f}, "
+          f"radiation energy drift {drift:.2e}", flush=True)
+    assert all(abs(r - 1.0) <= 0.2 for r in ratios), ratios
+    assert abs(shift - 1.0) <= 0.1, shift
+    assert drift <= TOL_MIXED
+
+
+def test_diffusion_copy_matches_oracle():
+    import oracle
+    wl = W.config5(shape=(64, 64, 32), width_cells=8.0, nsteps=20, precision="mixed")
+    s, st = _run_gpu(wl, "mixed", estimate_v=False)
+    assert st == 0
+    got = s.state()
+    s.close()
+    ref = oracle.run(wl, wl.nsteps, estimate_v=False)
+    errs = dict(E=_nerr(got["E"], ref.E), F=_nerr(got["F"], ref.F), T=_nerr(got["T"], ref.T),
+                I=_nerr(got["I"], ref.I))
+    print("diffusion 64x64x32 x 20 steps, mixed vs oracle:", errs, flush=True)
+    assert max(errs["E"], errs["F"], errs["T"]) <= TOL_MIXED, errs
