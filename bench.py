@@ -124,7 +124,9 @@ def serving(count: int, load: float, warm: int, seed: int = 4, fifo: bool = True
     FP32-mixed, Poisson arrivals).  The batched capacity is measured first in
     a closed loop over the first `warm` requests; arrivals are then scaled so
     that the offered load is `load` times that capacity, and the same trace
-    runs through the server and through the plain one-at-a-time path."""
+    runs through the server and through the plain one-at-a-time path.  The
+    capacity run takes the whole trace by default: a prefix of a heavy-tailed
+    mix need not carry its mean cost."""
     import numpy as np
     import torch
 
@@ -139,6 +141,7 @@ def serving(count: int, load: float, warm: int, seed: int = 4, fifo: bool = True
     work = np.array([wl.ncell * wl.nsteps * _nang(r["quad"]) for wl, r in zip(wls, reqs)],
                     dtype=np.float64)
     say(f"{count} requests generated")
+    warm = warm if 0 < warm < count else count
     cap = serve.run_batched(wls[:warm], [0.0] * warm, progress=say, **SERVE_DEFAULTS)
     rate = load * cap["throughput"] / work.mean()          # requests per second
     arrivals = np.cumsum([r["gap"] for r in reqs]) / rate
@@ -178,7 +181,8 @@ def main():
     ap.add_argument("--serve-requests", type=int, default=200,
                     help="requests of the serving trace (0: skip; 2000 = the full stream)")
     ap.add_argument("--serve-load", type=float, default=0.8)
-    ap.add_argument("--serve-warm", type=int, default=50)
+    ap.add_argument("--serve-warm", type=int, default=0,
+                    help="requests of the closed-loop capacity run (0: the whole trace)")
     ap.add_argument("--only-serve", action="store_true")
     ap.add_argument("--copy-probe", type=float, default=0.0,
                     help="profiling: time a plain device-to-device copy of this many GiB "
