@@ -224,6 +224,8 @@ void ctx_fill_args(const rt_ctx *c, double dt, const rt_fields *f, StepArgs &a) 
   a.estimate_v = (c->p.flags & RT_ESTIMATE_V) ? 1 : 0;
   a.mu = c->d_mu;
   a.w = c->d_w;
+  a.muf = c->d_muf;
+  a.wf = c->d_wf;
   a.ghost = c->d_ghost;
   a.faces = c->faces;
   if (f) {
@@ -299,7 +301,7 @@ int ctx_init_host(const rt_grid *g, const rt_angles *an, const rt_params *p, rt_
 namespace {
 // Scratch layout: offsets of the pieces in one block.
 struct Plan {
-  size_t mu, w, ghost, mom0, mom1, faces, partials, status, total;
+  size_t mu, w, muf, wf, ghost, mom0, mom1, faces, partials, status, total;
 };
 Plan plan_of(const rt_ctx *c) {
   Plan q;
@@ -312,6 +314,8 @@ Plan plan_of(const rt_ctx *c) {
   };
   q.mu = take(sizeof(double) * 3 * N);
   q.w = take(sizeof(double) * N);
+  q.muf = take(sizeof(float) * 3 * N);
+  q.wf = take(sizeof(float) * N);
   q.ghost = take(sizeof(double) * 6 * N);
   q.mom0 = take(sizeof(double) * kNmomX * nc);
   q.mom1 = take(sizeof(double) * kNmomX * nc);
@@ -330,6 +334,10 @@ int ctx_attach_scratch(rt_ctx *c, char *base, hipStream_t s) {
   const size_t N = c->nang;
   c->d_mu = reinterpret_cast<double *>(base + q.mu);
   c->d_w = reinterpret_cast<double *>(base + q.w);
+  c->d_muf = reinterpret_cast<float *>(base + q.muf);
+  c->d_wf = reinterpret_cast<float *>(base + q.wf);
+  c->h_muf.assign(c->h_mu.begin(), c->h_mu.end());
+  c->h_wf.assign(c->h_w.begin(), c->h_w.end());
   c->d_ghost = reinterpret_cast<double *>(base + q.ghost);
   c->mom[0] = reinterpret_cast<double *>(base + q.mom0);
   c->mom[1] = reinterpret_cast<double *>(base + q.mom1);
@@ -340,6 +348,10 @@ int ctx_attach_scratch(rt_ctx *c, char *base, hipStream_t s) {
       hip_ok(hipMemcpyAsync(c->d_mu, c->h_mu.data(), sizeof(double) * 3 * N,
                             hipMemcpyHostToDevice, s)) &&
       hip_ok(hipMemcpyAsync(c->d_w, c->h_w.data(), sizeof(double) * N, hipMemcpyHostToDevice,
+                            s)) &&
+      hip_ok(hipMemcpyAsync(c->d_muf, c->h_muf.data(), sizeof(float) * 3 * N,
+                            hipMemcpyHostToDevice, s)) &&
+      hip_ok(hipMemcpyAsync(c->d_wf, c->h_wf.data(), sizeof(float) * N, hipMemcpyHostToDevice,
                             s)) &&
       hip_ok(hipMemcpyAsync(c->d_ghost, c->h_ghost.data(), sizeof(double) * 6 * N,
                             hipMemcpyHostToDevice, s)) &&

@@ -29,6 +29,8 @@ struct StepArgs {
   int maxit, estimate_v;
   const double *mu;      // [3][nang]
   const double *w;       // [nang]
+  const float *muf;      // FP32 copies of mu and w (FP32 arithmetic)
+  const float *wf;
   const double *ghost;   // [3][2][nang] fixed-face ghost intensities
   const double *sa, *ss, *rho, *v;
   double *T;

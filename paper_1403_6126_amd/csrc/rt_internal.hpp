@@ -60,10 +60,12 @@ struct rt_ctx {
   bool all_periodic = true;
   double cfl_sum = 0.0;  // max over angles of sum_d |mu_d| / dx_d
   std::vector<double> h_mu, h_w, h_ghost;
+  std::vector<float> h_muf, h_wf;       // FP32 copies of the angle table
   // device memory: one block when carved from a caller's arena, else
   // separate hipMalloc allocations owned by the context
   bool owns_device = true;
   double *d_mu = nullptr, *d_w = nullptr, *d_ghost = nullptr;
+  float *d_muf = nullptr, *d_wf = nullptr;
   void *I[2] = {nullptr, nullptr};
   int cur = 0;
   double *mom[2] = {nullptr, nullptr};  // [13][ncell]: E, F, P, 3vJ

@@ -297,6 +297,8 @@ void rt_server::retire_one(Request *q) {
   q->t_done = now();
   q->ctx.h_mu.clear();
   q->ctx.h_w.clear();
+  q->ctx.h_muf.clear();
+  q->ctx.h_wf.clear();
   q->ctx.h_ghost.clear();
   q->state = kDone;
   completed += 1;

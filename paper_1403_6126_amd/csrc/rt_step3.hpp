@@ -147,6 +147,25 @@ __device__ __forceinline__ void waves_reduce(double (&x)[NV], double *buf, doubl
   }
 }
 
+// Unrolling of the transport loop over a wave's angles: full for FP64 (all
+// loads in flight at once), none for FP32 (registers).
+#ifndef RT_UNROLL_F64
+#define RT_UNROLL_F64 NS
+#endif
+#ifndef RT_UNROLL_F32
+#define RT_UNROLL_F32 1
+#endif
+
+// Entry i of an angle table in the arithmetic type: the FP32 copy (equal to
+// the conversion of the FP64 entry) saves a conversion per use.
+template <typename A>
+__device__ __forceinline__ A tab(const double *d, const float *f, int i) {
+  if constexpr (sizeof(A) == 4)
+    return f[i];
+  else
+    return d[i];
+}
+
 // Shared memory of one step body.
 // Values per reduction round: all 11 at once (the registers, not the LDS,
 // bound the blocks per CU of both storage types).
@@ -203,12 +222,13 @@ __device__ __forceinline__ void step3_tile(const StepArgs &p, int blk, int G, St
       const A dtdx = A(p.dt_dx[d]);
       const bool posR = s.uR > 0.0, posL = s.uL > 0.0;
       const bool zeroR = s.uR == 0.0, zeroL = s.uL == 0.0;
-      constexpr int UNR = sizeof(A) == 8 ? NS : 1;
+      constexpr int UNR = sizeof(A) == 8 ? RT_UNROLL_F64 : RT_UNROLL_F32;
 #pragma unroll UNR
       for (int k = 0; k < NS; ++k) {
           const int m = slot_m(k);
           const int mc = m < NA ? m : NA - 1;
-          const A n0 = A(p.mu[mc]), n1 = A(p.mu[NA + mc]), n2 = A(p.mu[2 * NA + mc]);
+          const A n0 = tab<A>(p.mu, p.muf, mc), n1 = tab<A>(p.mu, p.muf, NA + mc),
+                  n2 = tab<A>(p.mu, p.muf, 2 * NA + mc);
           const A mud = d == 0 ? n0 : d == 1 ? n1 : n2;
           if (m < NA && mud != A(0)) {  // uniform over the wave
           const S *Im = Iin + (size_t)m * N;
@@ -291,8 +311,9 @@ __device__ __forceinline__ void step3_tile(const StepArgs &p, int blk, int G, St
     pk[k] = A(0);
     const int m = slot_m(k);
     if (m >= NA) continue;
-    const A n0 = A(p.mu[m]), n1 = A(p.mu[NA + m]), n2 = A(p.mu[2 * NA + m]);
-    const A Wm = A(p.w[m]);
+    const A n0 = tab<A>(p.mu, p.muf, m), n1 = tab<A>(p.mu, p.muf, NA + m),
+            n2 = tab<A>(p.mu, p.muf, 2 * NA + m);
+    const A Wm = tab<A>(p.w, p.wf, m);
     const A t = n0 * Au0 + n1 * Au1 + n2 * Au2;
     const A D = D0 - dsa * t, aw = AW0 - dss * t;
     const A rDa = fast_rcp(D * aw);
@@ -394,7 +415,8 @@ __device__ __forceinline__ void step3_tile(const StepArgs &p, int blk, int G, St
     const int m = slot_m(k);
     if (m >= NA) continue;
     const double d0 = p.mu[m], d1 = p.mu[NA + m], d2 = p.mu[2 * NA + m];
-    const A t = A(d0) * Au0 + A(d1) * Au1 + A(d2) * Au2;
+    const A t = tab<A>(p.mu, p.muf, m) * Au0 + tab<A>(p.mu, p.muf, NA + m) * Au1 +
+                tab<A>(p.mu, p.muf, 2 * NA + m) * Au2;
     const A D = D0 - dsa * t, aw = AW0 - dss * t;
     const A rDa = fast_rcp(D * aw);
     const A e = E0 + A(3) * dsa * t;
