@@ -94,7 +94,7 @@ class Problem:
     """Problem description for the oracle (grid, angles, parameters)."""
 
     def __init__(self, wl, mu=None, w=None, estimate_v: bool = True,
-                 rtol: float = 1e-14, maxit: int = 64, ghost=None):
+                 rtol: float = 1e-14, maxit: int = 64, ghost=None, feedback: bool = False):
         if mu is None:
             mu, w = angle_set(wl.quad)
         self.wl = wl
@@ -125,6 +125,10 @@ class Problem:
         s.rtol = rtol
         s.maxit = maxit
         self.s = s
+        # gas feedback (Section 4.1 Step 7 with rho held fixed): after every
+        # step the gas momentum change of the step moves the velocity,
+        # v <- v + d(rho v)/rho
+        self.feedback = feedback
 
     @property
     def ptr(self):
@@ -183,14 +187,16 @@ def totals(prob: Problem, rho, T, E, F, dEgas=None, dEkin=None, dMom=None, I=Non
 
 
 class State:
-    """Evolving oracle state: I (nang, ncell), T, last moments and the
-    accumulated gas source terms of the steps taken so far."""
+    """Evolving oracle state: I (nang, ncell), T, the velocity (which moves
+    only with gas feedback), last moments and the accumulated gas source
+    terms of the steps taken so far."""
 
     def __init__(self, prob: Problem, I0=None, T0=None):
         wl = prob.wl
         self.prob = prob
         self.I = _f64(wl.init(prob.mu) if I0 is None else I0).copy()
         self.T = _f64(wl.T if T0 is None else T0).copy()
+        self.v = _f64(wl.v).reshape(3, wl.ncell).copy()
         nc = wl.ncell
         self.dEgas = np.zeros(nc)
         self.dEkin = np.zeros(nc)
@@ -203,15 +209,25 @@ class State:
         p = self.prob
         wl = p.wl
         dt = wl.dt if dt is None else dt
-        rho, sa, ss, v = _f64(wl.rho), _f64(wl.sigma_a), _f64(wl.sigma_s), _f64(wl.v)
+        rho, sa, ss = _f64(wl.rho), _f64(wl.sigma_a), _f64(wl.sigma_s)
         out = np.empty_like(self.I)
+        nc = wl.ncell
+        sEgas, sEkin, sMom = np.empty(nc), np.empty(nc), np.empty((3, nc))
         for _ in range(nsteps):
-            it = lib().or_step(p.ptr, dt, _dp(rho), _dp(sa), _dp(ss), _dp(v), _dp(self.I),
-                               _dp(out), _dp(self.T), _dp(self.dEgas), _dp(self.dEkin),
-                               _dp(self.dMom), _dp(self.E), _dp(self.F), _dp(self.Pr),
-                               1 if self.steps > 0 else 0)
+            # the exchange of this step alone, then added to the sums
+            it = lib().or_step(p.ptr, dt, _dp(rho), _dp(sa), _dp(ss), _dp(self.v), _dp(self.I),
+                               _dp(out), _dp(self.T), _dp(sEgas), _dp(sEkin), _dp(sMom),
+                               _dp(self.E), _dp(self.F), _dp(self.Pr), 0)
             if it < 0:
                 raise RuntimeError("oracle Newton iteration did not converge")
+            if self.steps == 0:
+                self.dEgas[:], self.dEkin[:], self.dMom[:] = sEgas, sEkin, sMom
+            else:
+                self.dEgas += sEgas
+                self.dEkin += sEkin
+                self.dMom += sMom
+            if p.feedback:
+                self.v += sMom / rho[None, :]
             self.newton_max = max(self.newton_max, it)
             self.I, out = out, self.I
             self.steps += 1
