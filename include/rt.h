@@ -63,6 +63,12 @@ enum { RT_FP64 = 0, RT_FP32_MIXED = 1 };
 enum { RT_QUAD_GAUSS_LEGENDRE = 0, RT_QUAD_LEVEL_SYMMETRIC = 1 };
 /* Flag: use the half-step velocity estimate of Section 4.5 (default on). */
 #define RT_ESTIMATE_V 1u
+/* Flag: gas feedback (Section 4.1 Step 7 with the density held fixed):
+ * after every step the gas momentum change of the step moves the flow,
+ * v <- v + d(rho v)/rho, in rt_fields.v, and the next step's interface flow
+ * speeds and IV follow (Section 5.2, equilibrium in a moving medium).  Angle
+ * sets of at most 320 directions; not for served requests. */
+#define RT_GAS_FEEDBACK 2u
 /* Number of entries of the totals vector. */
 #define RT_NTOT 12
 
@@ -90,7 +96,7 @@ typedef struct rt_params {
   double gamma;        /* adiabatic index > 1                               */
   double r_ideal;      /* ideal gas constant > 0; c_v = rho r/(gamma - 1)   */
   int precision;       /* RT_FP64 or RT_FP32_MIXED                          */
-  unsigned flags;      /* RT_ESTIMATE_V                                     */
+  unsigned flags;      /* RT_ESTIMATE_V | RT_GAS_FEEDBACK                   */
   double newton_rtol;  /* relative tolerance of the temperature Newton
                           iteration (e.g. 1e-14); <= 0 selects 1e-14        */
   int newton_maxit;    /* iteration limit (e.g. 64); <= 0 selects 64        */
@@ -102,7 +108,8 @@ typedef struct rt_fields { /* device arrays, [ncell] doubles unless noted */
   const double *rho;       /* density > 0                                  */
   double *T;               /* gas temperature, read at time n and
                               overwritten with T^{n+1}                     */
-  const double *v;         /* [3][ncell] flow velocity (held fixed)        */
+  double *v;               /* [3][ncell] flow velocity: held fixed, or
+                              updated in place with RT_GAS_FEEDBACK        */
 } rt_fields;
 
 typedef struct rt_out { /* device arrays; any pointer may be NULL */

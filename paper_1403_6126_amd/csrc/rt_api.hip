@@ -233,6 +233,7 @@ void ctx_fill_args(const rt_ctx *c, double dt, const rt_fields *f, StepArgs &a) 
     a.ss = f->sigma_s;
     a.rho = f->rho;
     a.v = f->v;
+    a.feedback = (c->p.flags & RT_GAS_FEEDBACK) ? 1 : 0;
     a.T = f->T;
   }
   a.status = c->status;
@@ -391,7 +392,13 @@ int ctx_step(rt_ctx *c, double dt, int nsteps, const rt_fields *f, rt_out *o, hi
 
 int ctx_step_range(rt_ctx *c, double dt, const rt_fields *f, rt_out *o, int k0, int k1,
                    int ntotal, hipStream_t s) {
+  const bool feedback = (c->p.flags & RT_GAS_FEEDBACK) != 0;
   for (int k = k0; k < k1; ++k) {
+    // with gas feedback the flow speeds of the interface table follow v
+    if (feedback && k > k0) {
+      const int st = ctx_prepare_call(c, dt, f, s);
+      if (st != RT_OK) return st;
+    }
     const int st = one_step(c, dt, f, nullptr, true, o, k == 0, k == ntotal - 1, s);
     if (st != RT_OK) return st;
   }
@@ -541,6 +548,7 @@ int rt_source_implicit(rt_ctx *c, double dt, const rt_fields *f, const void *dF,
                        void *stream) {
   if (!c || !fields_ok(f)) return RT_EINVAL;
   if (!c->I[0]) return RT_ESTATE;
+  if ((c->p.flags & RT_GAS_FEEDBACK) && !c->shape.waves) return RT_EUNSUPPORTED;
   if (!(dt > 0.0) || !std::isfinite(dt)) return RT_EINVAL;
   hipStream_t s = (hipStream_t)stream;
   int st = ensure_moments(c, s);
@@ -553,6 +561,7 @@ int rt_source_implicit(rt_ctx *c, double dt, const rt_fields *f, const void *dF,
 int rt_step(rt_ctx *c, double dt, int nsteps, const rt_fields *f, rt_out *o, void *stream) {
   if (!c || !fields_ok(f) || nsteps < 0) return RT_EINVAL;
   if (!c->I[0]) return RT_ESTATE;
+  if ((c->p.flags & RT_GAS_FEEDBACK) && !c->shape.waves) return RT_EUNSUPPORTED;
   int st = ctx_check_dt(c, dt);
   if (st != RT_OK) return st;
   return ctx_step(c, dt, nsteps, f, o, (hipStream_t)stream);

@@ -32,7 +32,9 @@ struct StepArgs {
   const float *muf;      // FP32 copies of mu and w (FP32 arithmetic)
   const float *wf;
   const double *ghost;   // [3][2][nang] fixed-face ghost intensities
-  const double *sa, *ss, *rho, *v;
+  const double *sa, *ss, *rho;
+  double *v;             // [3][ncell]; written only with feedback
+  int feedback;          // gas feedback: v <- v + d(rho v)/rho after the step
   double *T;
   const double *faces;   // [3][3][ncell] alpha, hv, u of the low face of each cell
   const double *mom_in;  // [13][ncell] E, F(3), P(6), 3vJ(3) of I^n

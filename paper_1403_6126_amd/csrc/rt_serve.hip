@@ -549,6 +549,7 @@ int rt_serve_submit(rt_server *s, const rt_request *r, long long *id) {
   *id = 0;
   if (r->nsteps < 1 || !r->sigma_a || !r->sigma_s || !r->rho || !r->T || !r->v)
     return RT_EINVAL;
+  if (r->params.flags & RT_GAS_FEEDBACK) return RT_EUNSUPPORTED;
   std::unique_ptr<Request> q(new (std::nothrow) Request());
   if (!q) return RT_ENOMEM;
   q->r = *r;

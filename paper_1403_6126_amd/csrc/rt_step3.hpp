@@ -452,16 +452,22 @@ __device__ __forceinline__ void step3_tile(const StepArgs &p, int blk, int G, St
        (mm0 * mm0 + mm1 * mm1 + mm2 * mm2)) /
       (2.0 * rho);
   const double deg = cv * (T - Tn) + ek;
+  // gas feedback (rho fixed): the momentum change of the step moves the flow;
+  // 3 v J of the new state, used by the next step's IV, takes the new v
+  const double vn0 = p.feedback ? v0 + dm0 / rho : v0;
+  const double vn1 = p.feedback ? v1 + dm1 / rho : v1;
+  const double vn2 = p.feedback ? v2 + dm2 / rho : v2;
   if (act) {
     // the per-cell stores are spread over the waves, 64 consecutive cells each
-    for (int f = g; f < 28; f += G) {
+    const int nf = p.feedback ? 31 : 28;
+    for (int f = g; f < nf; f += G) {
       double val;
       double *dst;
       if (f < 10) {
         val = mo[f];
         dst = p.mom_out + (size_t)f * N;
       } else if (f < 13) {
-        val = 3.0 * (f == 10 ? v0 : f == 11 ? v1 : v2) * mo[0] * (1.0 / kFourPi);
+        val = 3.0 * (f == 10 ? vn0 : f == 11 ? vn1 : vn2) * mo[0] * (1.0 / kFourPi);
         dst = p.mom_out + (size_t)f * N;
       } else if (f == 13) {
         val = T;
@@ -483,10 +489,14 @@ __device__ __forceinline__ void step3_tile(const StepArgs &p, int blk, int G, St
         if (!p.oF) continue;
         val = mo[f - 18];
         dst = p.oF + (size_t)(f - 19) * N;
-      } else {
+      } else if (f < 28) {
         if (!p.oP) continue;
         val = mo[f - 18];
         dst = p.oP + (size_t)(f - 22) * N;
+      } else {
+        // every wave has read this cell's v before the reductions above
+        val = f == 28 ? vn0 : f == 29 ? vn1 : vn2;
+        dst = p.v + (size_t)(f - 28) * N;
       }
       dst[c] = val;
     }

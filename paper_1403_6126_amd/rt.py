@@ -25,6 +25,7 @@ RT_BC_PERIODIC, RT_BC_FIXED, RT_BC_COPY, RT_BC_VACUUM = 0, 1, 2, 3
 RT_FP64, RT_FP32_MIXED = 0, 1
 RT_QUAD_GAUSS_LEGENDRE, RT_QUAD_LEVEL_SYMMETRIC = 0, 1
 RT_ESTIMATE_V = 1
+RT_GAS_FEEDBACK = 2
 RT_NTOT = 12
 RT_MAX_ANGLES = 1024
 

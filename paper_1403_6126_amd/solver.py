@@ -30,7 +30,7 @@ class Solver:
 
     def __init__(self, wl, precision: str | None = None, mu=None, w=None,
                  estimate_v: bool = True, I0=None, T0=None, newton_rtol=1e-14,
-                 newton_maxit=64, device="cuda"):
+                 newton_maxit=64, device="cuda", feedback: bool = False):
         import torch
         self.torch = torch
         self.wl = wl
@@ -45,8 +45,9 @@ class Solver:
         nc = wl.ncell
         self.ncell = nc
         grid = rt.make_grid(wl.ndim, wl.n, wl.dx, wl.bc)
-        params = rt.make_params(wl.C, wl.P, wl.gamma, wl.R, self.precision,
-                                rt.RT_ESTIMATE_V if estimate_v else 0, newton_rtol, newton_maxit)
+        flags = (rt.RT_ESTIMATE_V if estimate_v else 0) | (rt.RT_GAS_FEEDBACK if feedback else 0)
+        params = rt.make_params(wl.C, wl.P, wl.gamma, wl.R, self.precision, flags, newton_rtol,
+                                newton_maxit)
         self.ctx = rt.rt_create(grid, self.mu, self.w, params)
         dev = torch.device(device)
         f64 = dict(dtype=torch.float64, device=dev)
@@ -116,6 +117,7 @@ class Solver:
         """Host copies of the state and outputs (synchronises)."""
         self.torch.cuda.synchronize()
         return dict(I=self.current().double().cpu().numpy(), T=self.T.cpu().numpy(),
+                    v=self.v.cpu().numpy(),
                     E=self.E.cpu().numpy(), F=self.F.cpu().numpy(), P=self.P.cpu().numpy(),
                     dEgas=self.dEgas.cpu().numpy(), dMom=self.dMom.cpu().numpy(),
                     totals=self.totals.cpu().numpy())

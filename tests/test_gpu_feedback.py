@@ -1,0 +1,80 @@
+"""Gas feedback (RT_GAS_FEEDBACK) on the GPU against the oracle: the paper's
+equilibrium in a moving medium (Section 5.2) and a non-uniform 3D case in
+which the moving flow changes the interface speeds and IV of the next step.
+FP64 within 1e-12 normwise (the velocity included), FP32-mixed within 1e-5."""
+import numpy as np
+import pytest
+
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"fp64": 1e-12, "mixed": 1e-5}
+
+
+def _nerr(a, b):
+    den = np.abs(b).max()
+    return float(np.abs(a - b).max() / den) if den > 0 else float(np.abs(a - b).max())
+
+
+def _moving(sa, ss):
+    wl = W.small_case(2, (8, 8), ("ls", 4), seed=1, courant=0.4, C=10.0, P=1.0, kappa_a=0,
+                      kappa_s=0, vscale=0)
+    wl.dx = (1 / 32, 1 / 32, 1.0)
+    wl.rho[:] = 1
+    wl.T[:] = 1
+    wl.v[:] = 0
+    wl.v[0] = 3.0
+    wl.sigma_a[:] = sa
+    wl.sigma_s[:] = ss
+    wl.init = lambda mu, nc=wl.ncell: np.full((np.asarray(mu).shape[0], nc), 1 / (4 * np.pi))
+    return wl
+
+
+def _run(wl, nsteps, precision):
+    import oracle
+
+    from paper_1403_6126_amd.solver import Solver
+    ref = oracle.State(oracle.Problem(wl, feedback=True)).step(nsteps=nsteps)
+    s = Solver(wl, precision=precision, feedback=True)
+    s.step(nsteps)
+    st = s.state()
+    status = s.status()
+    s.close()
+    assert status == 0
+    errs = {k: _nerr(st[k], r) for k, r in (("I", ref.I), ("T", ref.T), ("E", ref.E),
+                                            ("F", ref.F), ("P", ref.Pr), ("v", ref.v))}
+    print(f"{wl.name} {precision} feedback, {nsteps} steps:", errs, flush=True)
+    assert max(errs.values()) <= TOL[precision], errs
+    return st
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("sa,ss", [(100.0, 0.0), (0.0, 100.0)])
+def test_moving_medium(sa, ss, precision):
+    wl = _moving(sa, ss)
+    st = _run(wl, 60, precision)
+    E, Pxx, Pyy, Fx = st["E"].mean(), st["P"][0].mean(), st["P"][1].mean(), st["F"][0].mean()
+    v = st["v"][0].mean()
+    # the paper's equilibrium: f_xx ~ 0.37, f_yy ~ 0.315, comoving flux zero
+    assert abs(Pxx / E - 0.37) <= 0.005 and abs(Pyy / E - 0.315) <= 0.005
+    assert abs(Fx - v * (E + Pxx) / wl.C) <= 1e-5 * Fx
+    assert v < 3.0
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_feedback_nonuniform(precision):
+    wl = W.small_case(3, (9, 8, 7), ("ls", 6), seed=81, vscale=0.05, kappa_a=1.0, kappa_s=1.0,
+                      rho_s=0.3, T_s=0.1, P=2.0)
+    _run(wl, 6, precision)
+
+
+def test_feedback_needs_the_wave_group_kernel():
+    from paper_1403_6126_amd import rt
+    from paper_1403_6126_amd.solver import Solver
+    wl = W.small_case(1, (20,), ("gl", 330), seed=82, courant=0.3)
+    s = Solver(wl, feedback=True)
+    with pytest.raises(rt.RTError) as ei:
+        s.step(1)
+    assert ei.value.status == rt.RT_EUNSUPPORTED
+    s.close()
