@@ -1,0 +1,21 @@
+"""Steady-state pin of the whole oracle step with copy and vacuum faces:
+the non-LTE atmosphere of paper Section 5.3.  With one direction per octant
+(Eddington closure) the steady state of the transfer equation is
+E_r(tau) = 1 - exp(-sqrt(3 eps) tau)/(1 + sqrt(eps)), which the time-dependent
+step reaches (here eps = 0.1) to the discretization error of 1280 cells."""
+import numpy as np
+
+import workloads as W
+
+
+def test_atmosphere_reaches_the_analytic_steady_state(orc):
+    eps = 0.1
+    wl = W.atmosphere(eps)
+    st = orc.State(orc.Problem(wl)).step(nsteps=8000)
+    tau = wl.meta["tau"]
+    Ea = 1.0 - np.exp(-np.sqrt(3 * eps) * tau) / (1.0 + np.sqrt(eps))
+    sel = (tau > 0.05) & (tau < 50.0)
+    assert np.abs(st.E - Ea)[sel].max() <= 2e-3
+    assert np.all(st.T == 1.0)               # the temperature is held
+    # the top of the atmosphere is darker for smaller eps: E(0) = sqrt(eps)/(1 + sqrt(eps))
+    assert abs(st.E[-1] - np.sqrt(eps) / (1 + np.sqrt(eps))) <= 2e-3

@@ -22,3 +22,4 @@ from .configs import (  # noqa: F401
     Workload, config1, config2, config3, config4_requests, config5, request_workload,
     small_case, equilibrium_intensity, moment_intensity, lognormal,
 )
+from .atmosphere import atmosphere  # noqa: F401
