@@ -69,6 +69,12 @@ enum { RT_QUAD_GAUSS_LEGENDRE = 0, RT_QUAD_LEVEL_SYMMETRIC = 1 };
  * speeds and IV follow (Section 5.2, equilibrium in a moving medium).  Angle
  * sets of at most 320 directions; not for served requests. */
 #define RT_GAS_FEEDBACK 2u
+/* Flag: the original transport that Section 4.2 starts from (Stone &
+ * Mihalas 1992): every interface at speed C (alpha = 1) and I itself
+ * upwinded, with no IV split.  Section 5.5 shows its numerical diffusion
+ * swamping the physical diffusion in optically thick media; kept for that
+ * comparison. */
+#define RT_ORIGINAL_TRANSPORT 4u
 /* Number of entries of the totals vector. */
 #define RT_NTOT 12
 
@@ -96,7 +102,8 @@ typedef struct rt_params {
   double gamma;        /* adiabatic index > 1                               */
   double r_ideal;      /* ideal gas constant > 0; c_v = rho r/(gamma - 1)   */
   int precision;       /* RT_FP64 or RT_FP32_MIXED                          */
-  unsigned flags;      /* RT_ESTIMATE_V | RT_GAS_FEEDBACK                   */
+  unsigned flags;      /* RT_ESTIMATE_V | RT_GAS_FEEDBACK |
+                          RT_ORIGINAL_TRANSPORT                             */
   double newton_rtol;  /* relative tolerance of the temperature Newton
                           iteration (e.g. 1e-14); <= 0 selects 1e-14        */
   int newton_maxit;    /* iteration limit (e.g. 64); <= 0 selects 64        */

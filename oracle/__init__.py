@@ -44,6 +44,7 @@ class _Problem(ct.Structure):
         ("ghost", (ct.POINTER(ct.c_double) * 2) * 3),
         ("C", ct.c_double), ("P", ct.c_double), ("gamma", ct.c_double), ("R", ct.c_double),
         ("estimate_v", ct.c_int), ("rtol", ct.c_double), ("maxit", ct.c_int),
+        ("original", ct.c_int),
     ]
 
 
@@ -94,7 +95,8 @@ class Problem:
     """Problem description for the oracle (grid, angles, parameters)."""
 
     def __init__(self, wl, mu=None, w=None, estimate_v: bool = True,
-                 rtol: float = 1e-14, maxit: int = 64, ghost=None, feedback: bool = False):
+                 rtol: float = 1e-14, maxit: int = 64, ghost=None, feedback: bool = False,
+                 original: bool = False):
         if mu is None:
             mu, w = angle_set(wl.quad)
         self.wl = wl
@@ -124,6 +126,9 @@ class Problem:
         s.estimate_v = 1 if estimate_v else 0
         s.rtol = rtol
         s.maxit = maxit
+        # the original transport (Section 4.2 before the reduced speed and the
+        # IV split; the Section 5.5 comparison)
+        s.original = 1 if original else 0
         self.s = s
         # gas feedback (Section 4.1 Step 7 with rho held fixed): after every
         # step the gas momentum change of the step moves the velocity,

@@ -114,6 +114,7 @@ static double line_I(const line_ctx *L, int k) {
 
 /* IV = 3 n.v J (Section 4.2), the velocity-dependent part of the intensity. */
 static double line_IV(const line_ctx *L, int k) {
+  if (L->p->original) return 0.0; /* no IV split: I~ = I, no IV flux */
   const long long c = line_cell(L, k);
   const double *n = L->p->mu + 3 * L->m;
   const double nv = n[0] * L->v[c] + n[1] * L->v[L->nc + c] + n[2] * L->v[2 * L->nc + c];
@@ -166,7 +167,7 @@ static double face_flux(const line_ctx *L, int k, double dt, const double *sa,
   const long long cL = line_cell(L, k - 1), cR = line_cell(L, k);
   /* Ghost opacities copy the edge cell. */
   const double sig = 0.5 * ((sa[cL] + ss[cL]) + (sa[cR] + ss[cR]));
-  const double alpha = alpha_of(sig, dl);
+  const double alpha = L->p->original ? 1.0 : alpha_of(sig, dl);
 
   double phi_t = 0.0;
   if (mu != 0.0) {

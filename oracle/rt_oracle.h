@@ -41,6 +41,10 @@ typedef struct or_problem {
   int estimate_v;        /* 1: half-step velocity estimate (Section 4.5)      */
   double rtol;           /* Newton relative tolerance                         */
   int maxit;             /* Newton iteration limit                            */
+  int original;          /* 1: the original transport of Stone & Mihalas 1992
+                            that Section 4.2 starts from (speed C, I itself
+                            upwinded, no IV split), as in the Section 5.5
+                            comparison                                       */
 } or_problem;
 
 /* Angular quadrature of I (Section 3): E = 4pi sum W I, F_k = 4pi sum W mu_k I,

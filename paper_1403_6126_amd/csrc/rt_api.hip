@@ -40,7 +40,7 @@ __global__ __launch_bounds__(kBlock) void k_faces(StepArgs p, double *faces, dou
     faces[(size_t)(d * 3 + 2) * N + c] = u;
   }
   const double J = mom[c] * (1.0 / kFourPi);
-  for (int k = 0; k < 3; ++k) mom[(size_t)(10 + k) * N + c] = 3.0 * p.v[(size_t)k * N + c] * J;
+  for (int k = 0; k < 3; ++k) mom[(size_t)(10 + k) * N + c] = p.ivfac * p.v[(size_t)k * N + c] * J;
 }
 
 __global__ __launch_bounds__(kVLanes) void k_totals(const double *partials, int nblocks,
@@ -200,11 +200,14 @@ int ctx_check_dt(const rt_ctx *c, double dt) {
 void ctx_fill_args(const rt_ctx *c, double dt, const rt_fields *f, StepArgs &a) {
   std::memset(&a, 0, sizeof(a));
   a.ndim = c->g.ndim;
+  a.ivfac = (c->p.flags & RT_ORIGINAL_TRANSPORT) ? 0.0 : 3.0;
   for (int d = 0; d < 3; ++d) {
     a.n[d] = c->g.n[d];
     for (int s = 0; s < 2; ++s) a.bc[d][s] = c->g.bc[d][s];
     a.dt_dx[d] = dt / c->g.dx[d];
-    a.dl10[d] = 10.0 * c->g.dx[d];
+    // the original transport has alpha = 1 at every interface (zero length
+    // scale in its optical depth) and no IV split (IV = 0, I~ = I)
+    a.dl10[d] = (c->p.flags & RT_ORIGINAL_TRANSPORT) ? 0.0 : 10.0 * c->g.dx[d];
   }
   a.stride[0] = 1;
   a.stride[1] = c->g.n[0];

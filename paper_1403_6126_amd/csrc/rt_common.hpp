@@ -24,7 +24,8 @@ struct StepArgs {
   int stride[3];
   double dt, C, invC, P, cvfac;  // cvfac = R/(gamma - 1)
   double dt_dx[3];               // dt / dx_d
-  double dl10[3];                // 10 dx_d (transport speed factor alpha)
+  double dl10[3];                // 10 dx_d (transport speed factor alpha; 0 gives alpha = 1)
+  double ivfac;                  // 3 in IV = 3 n.v J (0: no IV split, I~ = I)
   double vol, rtol;
   int maxit, estimate_v;
   const double *mu;      // [3][nang]

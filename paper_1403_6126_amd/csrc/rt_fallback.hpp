@@ -52,9 +52,9 @@ __device__ __forceinline__ void build_axis(const StepArgs &p, int c, const int q
     ax.kind[j] = kind;
     const double Jj = p.mom_in[cj] * (1.0 / kFourPi);
     const double vx = p.v[cj], vy = p.v[(size_t)p.ncell + cj], vz = p.v[2 * (size_t)p.ncell + cj];
-    ax.wv[j][0] = A(3.0 * vx * Jj);
-    ax.wv[j][1] = A(3.0 * vy * Jj);
-    ax.wv[j][2] = A(3.0 * vz * Jj);
+    ax.wv[j][0] = A(p.ivfac * vx * Jj);
+    ax.wv[j][1] = A(p.ivfac * vy * Jj);
+    ax.wv[j][2] = A(p.ivfac * vz * Jj);
     sig[j] = p.sa[cj] + p.ss[cj];
     vd[j] = p.v[(size_t)d * p.ncell + cj];
   }
@@ -151,7 +151,7 @@ __device__ __forceinline__ void build_cell(const StepArgs &p, int c, CellCtx<A> 
   const double Jc = p.mom_in[c] * (1.0 / kFourPi);
   const double vc[3] = {p.v[c], p.v[(size_t)p.ncell + c], p.v[2 * (size_t)p.ncell + c]};
 #pragma unroll
-  for (int k = 0; k < 3; ++k) cc.wc[k] = A(3.0 * vc[k] * Jc);
+  for (int k = 0; k < 3; ++k) cc.wc[k] = A(p.ivfac * vc[k] * Jc);
   const double sigc = p.sa[c] + p.ss[c];
 #pragma unroll
   for (int d = 0; d < 3; ++d)

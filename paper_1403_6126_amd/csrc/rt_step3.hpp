@@ -467,7 +467,7 @@ __device__ __forceinline__ void step3_tile(const StepArgs &p, int blk, int G, St
         val = mo[f];
         dst = p.mom_out + (size_t)f * N;
       } else if (f < 13) {
-        val = 3.0 * (f == 10 ? vn0 : f == 11 ? vn1 : vn2) * mo[0] * (1.0 / kFourPi);
+        val = p.ivfac * (f == 10 ? vn0 : f == 11 ? vn1 : vn2) * mo[0] * (1.0 / kFourPi);
         dst = p.mom_out + (size_t)f * N;
       } else if (f == 13) {
         val = T;

@@ -26,6 +26,7 @@ RT_FP64, RT_FP32_MIXED = 0, 1
 RT_QUAD_GAUSS_LEGENDRE, RT_QUAD_LEVEL_SYMMETRIC = 0, 1
 RT_ESTIMATE_V = 1
 RT_GAS_FEEDBACK = 2
+RT_ORIGINAL_TRANSPORT = 4
 RT_NTOT = 12
 RT_MAX_ANGLES = 1024
 

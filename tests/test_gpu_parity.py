@@ -233,3 +233,24 @@ def test_mixed_precision_within_1e5(ndim, shape, quad):
     errs["energy"] = abs(etot(st["totals"]) - etot(tref)) / abs(etot(tref))
     print("mixed errors", errs, flush=True)
     assert max(errs.values()) <= 1e-5, errs
+
+
+def test_original_transport_matches_oracle():
+    """RT_ORIGINAL_TRANSPORT (alpha = 1, no IV split; the Section 5.5
+    comparison) against the oracle's original transport."""
+    import oracle
+    wl = W.small_case(3, (13, 10, 9), ("ls", 6), seed=91, vscale=0.05, kappa_a=20.0,
+                      kappa_s=30.0, rho_s=0.3, T_s=0.1,
+                      bc=((W.BC_PERIODIC, W.BC_PERIODIC), (W.BC_FIXED, W.BC_VACUUM),
+                          (W.BC_COPY, W.BC_FIXED)), ghost_seed=9)
+    ref = oracle.run(wl, nsteps=4, original=True)
+    s = _solver(wl, original_transport=True)
+    s.step(4)
+    st = s.state()
+    status = s.status()
+    s.close()
+    assert status == 0
+    _compare(st, ref, TOL64)
+    # and it differs from the reduced-speed step
+    base = oracle.run(wl, nsteps=4)
+    assert _nerr(st["I"], base.I) > 1e-6

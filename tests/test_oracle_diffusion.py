@@ -11,8 +11,8 @@ The analytic solution is first order in v/C; the step keeps the paper's
 O(v^2/C^2) terms, which move the pulse faster by a relative 1.35 (v/C)^2
 (1.35% here), so the drift is checked to 2%.  At tau_s = 625 the physical
 variance growth is tiny and the check is that the scheme adds no more than
-a few times that much numerical diffusion: with the unreduced transport
-speed (alpha = 1) the numerical diffusion would be hundreds of times larger.
+a few times that much numerical diffusion: the original transport (speed C,
+no IV split) spreads the pulse over a hundred times faster there.
 """
 import numpy as np
 import pytest
@@ -73,3 +73,21 @@ def test_diffusion_very_thick(orc):
     assert abs(r["drift"] - 1.0) <= 0.02, r
     assert r["dvar"] <= 3.0, r
     assert r["peak"] >= 0.93, r
+
+
+def test_original_transport_is_dominated_by_numerical_diffusion(orc):
+    """Section 5.5: at tau = 625 per cell the original transport (speed C,
+    no IV split) spreads the pulse far faster than the physical diffusion,
+    which the reduced speed alpha C with the IV split follows."""
+    class Original:
+        State = orc.State
+
+        @staticmethod
+        def Problem(wl, mu=None, w=None, **kw):
+            return orc.Problem(wl, mu, w, original=True, **kw)
+
+    res, _ = _run(Original, 625.0, [1.0])
+    assert res[0]["dvar"] >= 100.0, res[0]
+    ref, _ = _run(orc, 625.0, [1.0])
+    assert ref[0]["dvar"] <= 3.0
+    print("dvar/2Dt: original", res[0]["dvar"], "reduced", ref[0]["dvar"])
