@@ -458,9 +458,19 @@ __device__ __forceinline__ void step3_tile(const StepArgs &p, int blk, int G, St
   const double vn1 = p.feedback ? v1 + dm1 / rho : v1;
   const double vn2 = p.feedback ? v2 + dm2 / rho : v2;
   if (act) {
-    // the per-cell stores are spread over the waves, 64 consecutive cells each
-    const int nf = p.feedback ? 31 : 28;
-    for (int f = g; f < nf; f += G) {
+    // The per-cell fields (0-9 the moments, 10-12 3vJ of the new state, 13
+    // T, 14 dEgas, 15-17 dMom, 18-27 the optional output moments) are spread
+    // over the waves, 64 consecutive cells each: wave g takes the fields
+    // f = g mod G.  The loop is unrolled so that every field number is a
+    // constant (no dynamic indexing of mo[]).  With FP32 storage the
+    // wave's share is tested on a uniform bit mask; FP64 storage, short of
+    // registers, measured faster with the remainder taken per field.
+    unsigned fmask = 0u;
+    if constexpr (sizeof(S) == 4)
+      for (int f = g; f < 28; f += G) fmask |= 1u << f;
+#pragma unroll
+    for (int f = 0; f < 28; ++f) {
+      if (sizeof(S) == 4 ? !((fmask >> f) & 1u) : f % G != g) continue;
       double val;
       double *dst;
       if (f < 10) {
@@ -489,16 +499,19 @@ __device__ __forceinline__ void step3_tile(const StepArgs &p, int blk, int G, St
         if (!p.oF) continue;
         val = mo[f - 18];
         dst = p.oF + (size_t)(f - 19) * N;
-      } else if (f < 28) {
+      } else {
         if (!p.oP) continue;
         val = mo[f - 18];
         dst = p.oP + (size_t)(f - 22) * N;
-      } else {
-        // every wave has read this cell's v before the reductions above
-        val = f == 28 ? vn0 : f == 29 ? vn1 : vn2;
-        dst = p.v + (size_t)(f - 28) * N;
       }
       dst[c] = val;
+    }
+    // gas feedback: the new velocity (every wave has read this cell's v
+    // before the reductions above)
+    if (p.feedback && g == G - 1) {
+      p.v[c] = vn0;
+      p.v[N + c] = vn1;
+      p.v[2 * N + c] = vn2;
     }
   }
   if (g == 0) {

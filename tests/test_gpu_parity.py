@@ -61,14 +61,16 @@ def test_config1_fp64_100_steps():
         assert abs(st["totals"][k] - tref[k]) <= 1e-12 * sc, (k, st["totals"][k], tref[k])
 
 
-def test_config2_full_size_sampled_step():
-    # 128^3, S8, FP64, the fused kernel in the benchmark's launch shape: after
-    # two GPU steps, one more GPU step is compared on sampled cells with one
-    # oracle step from the same state.
+@pytest.mark.parametrize("precision,tol", [("fp64", TOL64), ("mixed", 1e-5)])
+def test_config2_full_size_sampled_step(precision, tol):
+    # 128^3, S8, the fused kernel in the benchmark's launch shape (FP64, and
+    # FP32-mixed with its XCD block order): after two GPU steps, one more GPU
+    # step is compared on sampled cells with one oracle step from the same
+    # state.
     import oracle
     wl = W.config2()
-    s = _solver(wl)
-    print(f"case {wl.name} full size: 2 steps, then 1 compared step", flush=True)
+    s = _solver(wl, precision=precision)
+    print(f"case {wl.name} full size {precision}: 2 steps, then 1 compared step", flush=True)
     s.step(2)
     st0 = s.state()
     s.step(1)
@@ -85,7 +87,7 @@ def test_config2_full_size_sampled_step():
                Pr=st1["P"][:, cells], dEgas=st1["dEgas"][cells], dMom=st1["dMom"][:, cells])
     errs = {k: _nerr(got[k], ref[k]) for k in got}
     print("sampled errors", errs, flush=True)
-    assert max(errs.values()) <= TOL64, errs
+    assert max(errs.values()) <= tol, errs
 
 
 CASES = [
