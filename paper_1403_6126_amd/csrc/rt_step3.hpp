@@ -106,14 +106,15 @@ __device__ __forceinline__ void load_stencil(const StepArgs &p, int c, const int
   }
 }
 
-// Intensity of angle plane Im at a stencil cell, with the ghost kinds.
+// Intensity at a stencil cell from the value raw read at its (clamped) cell
+// of the angle plane, with the ghost kinds.
 template <typename S, typename A, bool PER>
-__device__ __forceinline__ A plane_load(const StepArgs &p, const S *Im, int idx, int kind,
-                                        int side, int d, int m, A mud) {
-  if (PER || kind == 0) return A(Im[idx]);
+__device__ __forceinline__ A plane_value(const StepArgs &p, S raw, int kind, int side, int d,
+                                         int m, A mud) {
+  if (PER || kind == 0) return A(raw);
   if (kind == 1) return A(p.ghost[(size_t)(d * 2 + side) * p.nang + m]);
   const bool outgoing = side == 0 ? (mud < A(0)) : (mud > A(0));
-  return outgoing ? A(Im[idx]) : A(0);
+  return outgoing ? A(raw) : A(0);
 }
 
 // Sum (or, for the last value when MINLAST, minimum) of NV values over the
@@ -154,6 +155,14 @@ __device__ __forceinline__ void waves_reduce(double (&x)[NV], double *buf, doubl
 #endif
 #ifndef RT_UNROLL_F32
 #define RT_UNROLL_F32 1
+#endif
+// Slots whose plane reads are in flight ahead of the transport arithmetic
+// (FP64 storage: one, as registers allow).
+#ifndef RT_PREFETCH_F64
+#define RT_PREFETCH_F64 1
+#endif
+#ifndef RT_PREFETCH_F32
+#define RT_PREFETCH_F32 3
 #endif
 
 // Entry i of an angle table in the arithmetic type: the FP32 copy (equal to
@@ -196,8 +205,6 @@ __device__ __forceinline__ void step3_tile(const StepArgs &p, int blk, int G, St
   const S *Iin = static_cast<const S *>(p.I_in);
   S *Iout = static_cast<S *>(p.I_out);
   const double C = p.C, P = p.P, dt = p.dt;
-  const double sa = p.sa[c], ss = p.ss[c], rho = p.rho[c], Tn = p.T[c];
-  const double v0 = p.v[c], v1 = p.v[N + c], v2 = p.v[2 * N + c];
   // angle of a slot (wave-uniform); valid when < NA, table reads clamped
   auto slot_m = [&](int s) { return (g + (s / KA) * G) * KA + (s % KA); };
 
@@ -223,32 +230,56 @@ __device__ __forceinline__ void step3_tile(const StepArgs &p, int blk, int G, St
       const bool posR = s.uR > 0.0, posL = s.uL > 0.0;
       const bool zeroR = s.uR == 0.0, zeroL = s.uL == 0.0;
       constexpr int UNR = sizeof(A) == 8 ? RT_UNROLL_F64 : RT_UNROLL_F32;
+      // the plane reads of a slot: cells -1 and +1 and the far upwind cell
+      // (-2 for mu_d > 0, else +2).  Those of the PF next slots are issued
+      // before the arithmetic of the current one, so that their latency
+      // overlaps it.
+      auto reads = [&](int k, S (&r)[3]) {
+        const int m = slot_m(k);
+        const int mc = m < NA ? m : NA - 1;
+        const S *Im = Iin + (size_t)mc * N;
+        r[0] = Im[s.idx[1]];
+        r[1] = Im[s.idx[2]];
+        r[2] = Im[tab<A>(p.mu, p.muf, d * NA + mc) > A(0) ? s.idx[0] : s.idx[3]];
+      };
+      constexpr int PF = sizeof(A) == 8 ? RT_PREFETCH_F64 : RT_PREFETCH_F32;
+      S q[PF][3];
+#pragma unroll
+      for (int j = 0; j < PF; ++j)
+        if (j < NS) reads(j, q[j]);
 #pragma unroll UNR
       for (int k = 0; k < NS; ++k) {
+          S r[3];
+#pragma unroll
+          for (int t = 0; t < 3; ++t) r[t] = q[0][t];
+#pragma unroll
+          for (int j = 0; j + 1 < PF; ++j)
+#pragma unroll
+            for (int t = 0; t < 3; ++t) q[j][t] = q[j + 1][t];
+          if (k + PF < NS) reads(k + PF, q[PF - 1]);
           const int m = slot_m(k);
           const int mc = m < NA ? m : NA - 1;
           const A n0 = tab<A>(p.mu, p.muf, mc), n1 = tab<A>(p.mu, p.muf, NA + mc),
                   n2 = tab<A>(p.mu, p.muf, 2 * NA + mc);
           const A mud = d == 0 ? n0 : d == 1 ? n1 : n2;
           if (m < NA && mud != A(0)) {  // uniform over the wave
-          const S *Im = Iin + (size_t)m * N;
           A IV[4];
 #pragma unroll
           for (int j = 0; j < 4; ++j) IV[j] = n0 * s.wv[j][0] + n1 * s.wv[j][1] + n2 * s.wv[j][2];
           const A IVc = n0 * wc0 + n1 * wc1 + n2 * wc2;
           const A Itc = Ic[k] - IVc * invC;
-          const A Im1 = plane_load<S, A, PER>(p, Im, s.idx[1], s.kind[1], 0, d, m, mud);
-          const A Ip1 = plane_load<S, A, PER>(p, Im, s.idx[2], s.kind[2], 1, d, m, mud);
+          const A Im1 = plane_value<S, A, PER>(p, r[0], s.kind[1], 0, d, m, mud);
+          const A Ip1 = plane_value<S, A, PER>(p, r[1], s.kind[2], 1, d, m, mud);
           const A Itm1 = Im1 - IV[1] * invC, Itp1 = Ip1 - IV[2] * invC;
           const A h = A(0.5) * (A(1) - AC * fabs(mud) * dtdx);
           A upR, upL;
           if (mud > A(0)) {
-            const A Im2 = plane_load<S, A, PER>(p, Im, s.idx[0], s.kind[0], 0, d, m, mud);
+            const A Im2 = plane_value<S, A, PER>(p, r[2], s.kind[0], 0, d, m, mud);
             const A Itm2 = Im2 - IV[0] * invC;
             upR = vl_face(Itm1, Itc, Itp1, h);
             upL = vl_face(Itm2, Itm1, Itc, h);
           } else {
-            const A Ip2 = plane_load<S, A, PER>(p, Im, s.idx[3], s.kind[3], 1, d, m, mud);
+            const A Ip2 = plane_value<S, A, PER>(p, r[2], s.kind[3], 1, d, m, mud);
             const A Itp2 = Ip2 - IV[3] * invC;
             upR = vl_face(Itp2, Itp1, Itc, h);
             upL = vl_face(Itp1, Itc, Itm1, h);
@@ -281,6 +312,11 @@ __device__ __forceinline__ void step3_tile(const StepArgs &p, int blk, int G, St
       }
     }
   }
+
+  // the cell's fields, first needed here (loaded after the transport so that
+  // they take no registers there)
+  const double sa = p.sa[c], ss = p.ss[c], rho = p.rho[c], Tn = p.T[c];
+  const double v0 = p.v[c], v1 = p.v[N + c], v2 = p.v[2 * N + c];
 
   // ---------------------------------- Step 3: velocity estimate (per cell)
   double u0 = v0, u1 = v1, u2 = v2;
