@@ -23,3 +23,4 @@ from .configs import (  # noqa: F401
     small_case, equilibrium_intensity, moment_intensity, lognormal,
 )
 from .atmosphere import atmosphere  # noqa: F401
+from .beams import plane_directions, direction_at, shadow_density, shadow2d  # noqa: F401
