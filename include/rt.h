@@ -167,6 +167,20 @@ int rt_current_intensity(rt_ctx *ctx, void **I_cur);
  * the ghost values of J, v and the opacities copy the edge cell. */
 int rt_set_fixed_bc(rt_ctx *ctx, int axis, int side, const double *I_ghost);
 
+/* Position-dependent ghost intensities for an RT_BC_FIXED face, for beams
+ * that enter through part of a face (the crossing beams of Section 5.4):
+ * host array [nang][nface], nface = ncell / n[axis], the face cells ordered
+ * by the two other axes with the lower one fastest (axis 0: y + n[1] z;
+ * axis 1: x + n[0] z; axis 2: x + n[0] y).  Both ghost layers take the
+ * value of their face cell; the ghost values of J, v and the opacities copy
+ * the edge cell, as with rt_set_fixed_bc.  The library copies the array
+ * into device memory that it owns until rt_destroy; a later rt_set_fixed_bc
+ * on the face replaces it by an angle table again.  Synchronises the device
+ * when it replaces a table.  RT_EINVAL for a bad axis or side or a face that
+ * is not RT_BC_FIXED; RT_ENOMEM when the table cannot be allocated;
+ * RT_EDEVICE when the copy fails. */
+int rt_set_fixed_bc_face(rt_ctx *ctx, int axis, int side, const double *I_ghost);
+
 /* Angular moments of the current intensities (Section 3) into out->Er, Fr,
  * Pr, and into the context's moment fields used by the next step. */
 int rt_moments(rt_ctx *ctx, rt_out *out, void *stream);

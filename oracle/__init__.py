@@ -45,6 +45,7 @@ class _Problem(ct.Structure):
         ("C", ct.c_double), ("P", ct.c_double), ("gamma", ct.c_double), ("R", ct.c_double),
         ("estimate_v", ct.c_int), ("rtol", ct.c_double), ("maxit", ct.c_int),
         ("original", ct.c_int),
+        ("ghost_face", (ct.POINTER(ct.c_double) * 2) * 3),
     ]
 
 
@@ -122,6 +123,14 @@ class Problem:
                     g = _f64(ghost[(d, side)])
                     self._keep.append(g)
                     s.ghost[d][side] = _dp(g)
+        # position-dependent tables of fixed faces (beams through part of a
+        # face, Section 5.4): (nang, cells of the face)
+        gface = getattr(wl, "ghost_face", None)
+        if gface is not None:
+            for (d, side), g in gface(self.mu).items():
+                g = _f64(g)
+                self._keep.append(g)
+                s.ghost_face[d][side] = _dp(g)
         s.C, s.P, s.gamma, s.R = wl.C, wl.P, wl.gamma, wl.R
         s.estimate_v = 1 if estimate_v else 0
         s.rtol = rtol

@@ -105,7 +105,14 @@ static double line_I(const line_ctx *L, int k) {
   const int side = k < 0 ? 0 : 1;
   const int bc = p->bc[L->d][side];
   if (bc == OR_BC_PERIODIC) return L->I[(long long)L->m * L->nc + line_cell(L, k)];
-  if (bc == OR_BC_FIXED) return p->ghost[L->d][side][L->m];
+  if (bc == OR_BC_FIXED) {
+    const double *f = p->ghost_face[L->d][side];
+    if (!f) return p->ghost[L->d][side][L->m];
+    /* the face cell of the line: its coordinates on the two other axes */
+    const int a = L->d == 0 ? 1 : 0, b = L->d == 2 ? 1 : 2;
+    const long long nface = (long long)p->n[a] * p->n[b];
+    return f[(long long)L->m * nface + L->base[a] + (long long)p->n[a] * L->base[b]];
+  }
   const double mu = p->mu[3 * L->m + L->d];
   const int outgoing = side == 0 ? (mu < 0) : (mu > 0);
   if (bc == OR_BC_VACUUM && !outgoing) return 0.0;

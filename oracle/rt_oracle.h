@@ -45,6 +45,11 @@ typedef struct or_problem {
                             that Section 4.2 starts from (speed C, I itself
                             upwinded, no IV split), as in the Section 5.5
                             comparison                                       */
+  const double *ghost_face[3][2]; /* [nang][nface] position-dependent ghost
+                            intensities of an OR_BC_FIXED face, or NULL for
+                            its angle table; nface = cells of the face, in
+                            order of the two other axes, lower one fastest
+                            (beams through part of a face, Section 5.4)    */
 } or_problem;
 
 /* Angular quadrature of I (Section 3): E = 4pi sum W I, F_k = 4pi sum W mu_k I,

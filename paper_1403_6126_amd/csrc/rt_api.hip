@@ -230,6 +230,7 @@ void ctx_fill_args(const rt_ctx *c, double dt, const rt_fields *f, StepArgs &a) 
   a.muf = c->d_muf;
   a.wf = c->d_wf;
   a.ghost = c->d_ghost;
+  for (int f = 0; f < 6; ++f) a.gface[f] = c->d_gface[f];
   a.faces = c->faces;
   if (f) {
     a.sa = f->sigma_a;
@@ -474,6 +475,8 @@ int rt_destroy(rt_ctx *c) {
   hipDeviceSynchronize();
   // the scratch block starts at the angle table
   if (c->owns_device && c->d_mu) hipFree(c->d_mu);
+  for (auto f : c->d_gface)
+    if (f) hipFree(f);
   for (auto &pr : c->pending) {
     hipEventDestroy(pr.first);
     hipEventDestroy(pr.second);
@@ -502,9 +505,35 @@ int rt_current_intensity(rt_ctx *c, void **cur) {
 int rt_set_fixed_bc(rt_ctx *c, int axis, int side, const double *tab) {
   if (!c || !tab || axis < 0 || axis >= c->g.ndim || side < 0 || side > 1) return RT_EINVAL;
   if (c->g.bc[axis][side] != RT_BC_FIXED) return RT_EINVAL;
-  const size_t off = (size_t)(axis * 2 + side) * c->nang;
+  const int f = axis * 2 + side;
+  const size_t off = (size_t)f * c->nang;
   std::memcpy(&c->h_ghost[off], tab, sizeof(double) * c->nang);
   if (!hip_ok(hipMemcpy(c->d_ghost + off, tab, sizeof(double) * c->nang, hipMemcpyHostToDevice)))
+    return RT_EDEVICE;
+  // the angle table replaces a position-dependent one
+  if (c->d_gface[f]) {
+    hipDeviceSynchronize();
+    hipFree(c->d_gface[f]);
+    c->d_gface[f] = nullptr;
+  }
+  return RT_OK;
+}
+
+int rt_set_fixed_bc_face(rt_ctx *c, int axis, int side, const double *tab) {
+  if (!c || !tab || axis < 0 || axis >= c->g.ndim || side < 0 || side > 1) return RT_EINVAL;
+  if (c->g.bc[axis][side] != RT_BC_FIXED || !c->owns_device) return RT_EINVAL;
+  const int f = axis * 2 + side;
+  const size_t n = (size_t)c->nang * (size_t)(c->ncell / c->g.n[axis]);
+  if (!c->d_gface[f]) {
+    if (hipMalloc(&c->d_gface[f], sizeof(double) * n) != hipSuccess) {
+      c->d_gface[f] = nullptr;
+      clear_stale_error();
+      return RT_ENOMEM;
+    }
+  } else {
+    hipDeviceSynchronize();  // a step in flight may still read the table
+  }
+  if (!hip_ok(hipMemcpy(c->d_gface[f], tab, sizeof(double) * n, hipMemcpyHostToDevice)))
     return RT_EDEVICE;
   return RT_OK;
 }

@@ -33,6 +33,8 @@ struct StepArgs {
   const float *muf;      // FP32 copies of mu and w (FP32 arithmetic)
   const float *wf;
   const double *ghost;   // [3][2][nang] fixed-face ghost intensities
+  const double *gface[6];  // per face (axis*2 + side): [nang][ncell / n[axis]]
+                           // position-dependent ghosts of a fixed face, or null
   const double *sa, *ss, *rho;
   double *v;             // [3][ncell]; written only with feedback
   int feedback;          // gas feedback: v <- v + d(rho v)/rho after the step
@@ -67,6 +69,18 @@ __device__ __forceinline__ A upwind_face(A up2, A up1, A dn1, A h) {
 }
 
 // alpha = sqrt((1 - exp(-tau))/tau), tau = (10 dl sigma)^2, alpha(0) = 1
+// Ghost intensity of angle m beside edge cell e of the fixed face (d, side):
+// from the face's position-dependent table when it has one (face cells in
+// order of the two other axes, lower axis fastest), else from its angle
+// table.  Both ghost layers take the value.
+__device__ __forceinline__ double fixed_ghost(const StepArgs &p, int d, int side, int m, int e) {
+  const double *f = p.gface[d * 2 + side];
+  if (!f) return p.ghost[(size_t)(d * 2 + side) * p.nang + m];
+  const int n0 = p.n[0], n01 = p.n[0] * p.n[1];
+  const int fi = d == 0 ? e / n0 : d == 1 ? e % n0 + n0 * (e / n01) : e % n01;
+  return f[(size_t)m * (size_t)(p.ncell / p.n[d]) + fi];
+}
+
 __device__ __forceinline__ double alpha_of(double sigma, double dl10) {
   const double s = dl10 * sigma;
   const double tau = s * s;

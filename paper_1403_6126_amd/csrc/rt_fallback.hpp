@@ -72,7 +72,7 @@ __device__ __forceinline__ A load_I(const StepArgs &p, const S *Im, const Axis<A
                                     int d, int m, A mud) {
   if (PER || ax.kind[j] == 0) return A(Im[ax.idx[j]]);
   const int side = j < 2 ? 0 : 1;
-  if (ax.kind[j] == 1) return A(p.ghost[(size_t)(d * 2 + side) * p.nang + m]);
+  if (ax.kind[j] == 1) return A(fixed_ghost(p, d, side, m, ax.idx[j]));
   const bool outgoing = side == 0 ? (mud < A(0)) : (mud > A(0));
   return outgoing ? A(Im[ax.idx[j]]) : A(0);
 }

@@ -65,6 +65,9 @@ struct rt_ctx {
   // separate hipMalloc allocations owned by the context
   bool owns_device = true;
   double *d_mu = nullptr, *d_w = nullptr, *d_ghost = nullptr;
+  // position-dependent ghost tables of fixed faces (axis*2 + side), each its
+  // own allocation owned by the context
+  double *d_gface[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
   float *d_muf = nullptr, *d_wf = nullptr;
   void *I[2] = {nullptr, nullptr};
   int cur = 0;

@@ -107,12 +107,12 @@ __device__ __forceinline__ void load_stencil(const StepArgs &p, int c, const int
 }
 
 // Intensity at a stencil cell from the value raw read at its (clamped) cell
-// of the angle plane, with the ghost kinds.
+// idx of the angle plane, with the ghost kinds.
 template <typename S, typename A, bool PER>
-__device__ __forceinline__ A plane_value(const StepArgs &p, S raw, int kind, int side, int d,
-                                         int m, A mud) {
+__device__ __forceinline__ A plane_value(const StepArgs &p, S raw, int idx, int kind, int side,
+                                         int d, int m, A mud) {
   if (PER || kind == 0) return A(raw);
-  if (kind == 1) return A(p.ghost[(size_t)(d * 2 + side) * p.nang + m]);
+  if (kind == 1) return A(fixed_ghost(p, d, side, m, idx));
   const bool outgoing = side == 0 ? (mud < A(0)) : (mud > A(0));
   return outgoing ? A(raw) : A(0);
 }
@@ -268,18 +268,18 @@ __device__ __forceinline__ void step3_tile(const StepArgs &p, int blk, int G, St
           for (int j = 0; j < 4; ++j) IV[j] = n0 * s.wv[j][0] + n1 * s.wv[j][1] + n2 * s.wv[j][2];
           const A IVc = n0 * wc0 + n1 * wc1 + n2 * wc2;
           const A Itc = Ic[k] - IVc * invC;
-          const A Im1 = plane_value<S, A, PER>(p, r[0], s.kind[1], 0, d, m, mud);
-          const A Ip1 = plane_value<S, A, PER>(p, r[1], s.kind[2], 1, d, m, mud);
+          const A Im1 = plane_value<S, A, PER>(p, r[0], s.idx[1], s.kind[1], 0, d, m, mud);
+          const A Ip1 = plane_value<S, A, PER>(p, r[1], s.idx[2], s.kind[2], 1, d, m, mud);
           const A Itm1 = Im1 - IV[1] * invC, Itp1 = Ip1 - IV[2] * invC;
           const A h = A(0.5) * (A(1) - AC * fabs(mud) * dtdx);
           A upR, upL;
           if (mud > A(0)) {
-            const A Im2 = plane_value<S, A, PER>(p, r[2], s.kind[0], 0, d, m, mud);
+            const A Im2 = plane_value<S, A, PER>(p, r[2], s.idx[0], s.kind[0], 0, d, m, mud);
             const A Itm2 = Im2 - IV[0] * invC;
             upR = vl_face(Itm1, Itc, Itp1, h);
             upL = vl_face(Itm2, Itm1, Itc, h);
           } else {
-            const A Ip2 = plane_value<S, A, PER>(p, r[2], s.kind[3], 1, d, m, mud);
+            const A Ip2 = plane_value<S, A, PER>(p, r[2], s.idx[3], s.kind[3], 1, d, m, mud);
             const A Itp2 = Ip2 - IV[3] * invC;
             upR = vl_face(Itp2, Itp1, Itc, h);
             upL = vl_face(Itp1, Itc, Itm1, h);

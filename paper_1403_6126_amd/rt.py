@@ -109,6 +109,8 @@ SIGNATURES = [
     ("rt_bind_intensity", ct.c_int, [ct.c_void_p, ct.c_void_p, ct.c_void_p]),
     ("rt_current_intensity", ct.c_int, [ct.c_void_p, ct.POINTER(ct.c_void_p)]),
     ("rt_set_fixed_bc", ct.c_int, [ct.c_void_p, ct.c_int, ct.c_int, ct.POINTER(ct.c_double)]),
+    ("rt_set_fixed_bc_face", ct.c_int, [ct.c_void_p, ct.c_int, ct.c_int,
+                                        ct.POINTER(ct.c_double)]),
     ("rt_moments", ct.c_int, [ct.c_void_p, ct.POINTER(rt_out), ct.c_void_p]),
     ("rt_transport", ct.c_int, [ct.c_void_p, ct.c_double, ct.POINTER(rt_fields), ct.c_void_p,
                                 ct.c_void_p]),
@@ -235,6 +237,13 @@ def rt_current_intensity(ctx: int) -> int:
 def rt_set_fixed_bc(ctx: int, axis: int, side: int, table: np.ndarray) -> None:
     t = np.ascontiguousarray(table, dtype=np.float64)
     _check(lib().rt_set_fixed_bc(ct.c_void_p(ctx), axis, side, _dptr(t)), "rt_set_fixed_bc")
+
+
+def rt_set_fixed_bc_face(ctx: int, axis: int, side: int, table: np.ndarray) -> None:
+    """table: (nang, ncell // n[axis]) ghost intensities of the face cells."""
+    t = np.ascontiguousarray(table, dtype=np.float64)
+    _check(lib().rt_set_fixed_bc_face(ct.c_void_p(ctx), axis, side, _dptr(t)),
+           "rt_set_fixed_bc_face")
 
 
 def make_fields(sigma_a, sigma_s, rho, T, v) -> rt_fields:

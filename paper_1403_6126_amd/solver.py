@@ -80,6 +80,10 @@ class Solver:
             for (axis, side), tab in tables.items():
                 if axis < wl.ndim and wl.bc[axis][side] == rt.RT_BC_FIXED:
                     rt.rt_set_fixed_bc(self.ctx, axis, side, tab)
+        if getattr(wl, "ghost_face", None) is not None:
+            for (axis, side), tab in wl.ghost_face(self.mu).items():
+                if axis < wl.ndim and wl.bc[axis][side] == rt.RT_BC_FIXED:
+                    rt.rt_set_fixed_bc_face(self.ctx, axis, side, tab)
         self.fields = rt.make_fields(self.sa, self.ss, self.rho, self.T, self.v)
         self.out = rt.make_out(self.E, self.F, self.P, self.dEgas, self.dMom, self.totals)
 

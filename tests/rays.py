@@ -109,3 +109,32 @@ def ray_energy(wl, cells, ds=2e-3):
         E += FOUR_PI * w[m] * ray_intensity(X[cells], Y[cells], mu[m, :2], sig, B, entry,
                                             wl.meta["box"], ds=ds)
     return E
+
+
+# ------------------------------------ the crossing beams (Section 5.4)
+def beam_stats(wl, I):
+    """Per-row statistics of the crossing beams from the intensities
+    I (nang, ncell): the x-flux-weighted row flux 4 pi sum_m w_m mu_y I_m dx,
+    the flux injected through the bottom face, and for each beam direction
+    its centroid along x (circular mean over the periodic axis) and its
+    variance about it, row by row."""
+    mu, w = np.asarray(wl.quad[1]), np.asarray(wl.quad[2])
+    nx, ny = wl.n[0], wl.n[1]
+    I = np.asarray(I).reshape(len(w), ny, nx)
+    xs = (np.arange(nx) + 0.5) * wl.dx[0]
+    ys = (np.arange(ny) + 0.5) * wl.dx[1]
+    row = FOUR_PI * np.einsum("m,m,mji->j", w, mu[:, 1], I) * wl.dx[0]
+    injected = FOUR_PI * wl.meta["beam"] * wl.dx[0] * sum(
+        w[m] * mu[m, 1] * wl.meta["window_cells"][k] for k, m in enumerate(wl.meta["beams"]))
+    ang = 2.0 * np.pi * xs
+    beams = []
+    for k, m in enumerate(wl.meta["beams"]):
+        cx = np.arctan2((I[m] * np.sin(ang)).sum(1), (I[m] * np.cos(ang)).sum(1)) / (2 * np.pi)
+        cx %= 1.0
+        d = (xs[None, :] - cx[:, None] + 0.5) % 1.0 - 0.5
+        var = (I[m] * d ** 2).sum(1) / I[m].sum(1)
+        # straight line from the window centre at 45 degrees, wrapped
+        expect = (wl.meta["centres"][k] + np.sign(mu[m, 0]) * ys) % 1.0
+        off = (cx - expect + 0.5) % 1.0 - 0.5
+        beams.append(dict(centroid_error=off, var=var))
+    return dict(ys=ys, row_flux=row, injected=injected, beams=beams)

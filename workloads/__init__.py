@@ -23,4 +23,6 @@ from .configs import (  # noqa: F401
     small_case, equilibrium_intensity, moment_intensity, lognormal,
 )
 from .atmosphere import atmosphere  # noqa: F401
-from .beams import plane_directions, direction_at, shadow_density, shadow2d  # noqa: F401
+from .beams import (  # noqa: F401
+    crossing_beams, direction_at, plane_directions, shadow2d, shadow_density,
+)

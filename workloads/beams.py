@@ -9,7 +9,13 @@
   bottom face at +14 degrees and through the top face at -14 degrees; the
   right face copies the last active cells.  The flow is not evolved.
 
-Readings (the paper leaves them open): the directions are an in-plane set
+* ``crossing_beams``: two beams crossing vacuum (Section 5.4).  Box
+  L_x = 1, L_y = 4 at 128 x 512 cells (the paper also runs 256 x 1024),
+  periodic along x, zero absorption and scattering; beams enter through the
+  bottom face at 45 degrees to the +x and to the -x axis, wrap around
+  through the periodic x faces, cross and leave through the top.
+
+Readings of the shadow test (the paper leaves them open): the directions are an in-plane set
 of 90 equally weighted directions 4 degrees apart, which holds +-14 degrees
 exactly; the gas temperature, and with it sigma_a, keeps its initial value
 (a heat capacity so large that the temperature step leaves T unchanged),
@@ -17,6 +23,14 @@ and the velocity estimate is off (v = 0 throughout), so the steady state is
 that of pure absorption and emission along each direction; the faces with
 beams give the background equilibrium intensity 1/(4 pi) to every other
 incoming direction.
+
+Readings of the crossing beams: each beam enters through a window of width
+1/8 of the bottom face, the +x beam centred at x = 1/4 and the -x beam at
+x = 3/4, so that they cross inside the box every 1/2 in height; unit beam
+intensity, zero elsewhere on the face and zero initial intensity; C = 1;
+the directions are the four in-plane ones at 45 + 90 k degrees; the top face
+is a vacuum face (outgoing copied, incoming zero), through which the beams
+leave.
 """
 from __future__ import annotations
 
@@ -24,7 +38,8 @@ import math
 
 import numpy as np
 
-from .configs import BC_COPY, BC_FIXED, BC_PERIODIC, FOUR_PI, Workload, _cell_centres
+from .configs import (BC_COPY, BC_FIXED, BC_PERIODIC, BC_VACUUM, FOUR_PI, Workload,
+                      _cell_centres)
 
 HEAT_CAPACITY_R = 1e30
 BEAM_INTENSITY = 103.13
@@ -85,4 +100,40 @@ def shadow2d(nx: int = 512, ny: int = 256, nphi: int = 90, nsteps: int = 3000,
     wl.meta.update(beams=(up, down), beam=beam, box=((-0.5, 0.5), (-0.3, 0.3)),
                    background=1.0 / FOUR_PI, estimate_v=False,
                    crossing_time=math.hypot(1.0, 0.6) / C)
+    return wl
+
+
+def crossing_beams(nx: int = 128, ny: int = 512, nsteps: int = 2400, C: float = 1.0,
+                   courant: float = 0.4, precision: str = "fp64", width: float = 0.125,
+                   centres=(0.25, 0.75), beam: float = 1.0) -> Workload:
+    n = (nx, ny, 1)
+    dx = (1.0 / nx, 4.0 / ny, 1.0)
+    nc = nx * ny
+    mu, w = plane_directions(4, 45.0)
+    right, left = direction_at(mu, 45.0), direction_at(mu, 135.0)
+    bc = ((BC_PERIODIC, BC_PERIODIC), (BC_FIXED, BC_VACUUM), (BC_PERIODIC, BC_PERIODIC))
+    wl = Workload(name=f"crossing-beams-{nx}x{ny}", n=n, ndim=2, dx=dx, bc=bc,
+                  quad=("table", mu, w), C=C, P=1.0, courant=courant, nsteps=nsteps,
+                  precision=precision, rho=np.ones(nc), T=np.ones(nc), v=np.zeros((3, nc)),
+                  sigma_a=np.zeros(nc), sigma_s=np.zeros(nc))
+    wl.init = lambda m: np.zeros((np.asarray(m).shape[0], nc))
+    xs = (np.arange(nx) + 0.5) / nx
+
+    def window(c):
+        dist = np.abs((xs - c + 0.5) % 1.0 - 0.5)
+        return (dist < 0.5 * width).astype(np.float64)
+
+    def ghost(m):
+        return {(1, 0): np.zeros(np.asarray(m).shape[0])}
+
+    def ghost_face(m, right=right, left=left):
+        g = np.zeros((np.asarray(m).shape[0], nx))
+        g[right] = beam * window(centres[0])
+        g[left] = beam * window(centres[1])
+        return {(1, 0): g}
+    wl.ghost = ghost
+    wl.ghost_face = ghost_face
+    wl.meta.update(beams=(right, left), centres=centres, width=width, beam=beam,
+                   window_cells=(window(centres[0]).sum(), window(centres[1]).sum()),
+                   crossing_time=4.0 * math.sqrt(2.0) / C)
     return wl

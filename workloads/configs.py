@@ -50,6 +50,9 @@ class Workload:
     init: Optional[Callable[[np.ndarray], np.ndarray]] = None
     # fixed-boundary tables from the angle table: {(axis, side): (nang,)}
     ghost: Optional[Callable[[np.ndarray], Dict[Tuple[int, int], np.ndarray]]] = None
+    # position-dependent fixed-boundary tables: {(axis, side): (nang, nface)},
+    # face cells ordered by the two other axes, lower axis fastest
+    ghost_face: Optional[Callable[[np.ndarray], Dict[Tuple[int, int], np.ndarray]]] = None
     meta: Dict = field(default_factory=dict)
 
     @property
