@@ -69,3 +69,66 @@ def test_crossing_full_size():
         assert dev <= 1e-2 and cen <= 1.0 and mid < 0.05 * E.max()
     for a, b in zip(growth[128], growth[256]):
         assert 0.4 < b / a < 0.6
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_uniform_face_table_equals_angle_table(precision):
+    """A position-dependent table that is the same on every face cell gives
+    the step of the per-angle table bit for bit (both kernels read the same
+    value for every ghost), on fixed faces of all six sides of a 3D grid
+    and of the thread-per-cell kernel (more than 320 directions); a later
+    rt_set_fixed_bc puts the face back on its angle table."""
+    from paper_1403_6126_amd import rt
+    from paper_1403_6126_amd.solver import Solver
+    fixed = ((rt.RT_BC_FIXED, rt.RT_BC_FIXED),) * 3
+    cases = [W.small_case(3, (12, 10, 9), ("ls", 8), seed=81, bc=fixed, ghost_seed=82,
+                          precision=precision),
+             W.small_case(1, (40,), ("gl", 330), seed=83, bc=fixed, ghost_seed=84,
+                          precision=precision)]
+    for wl in cases:
+        ref = Solver(wl, precision=precision)
+        ref.step(4)
+        a = ref.state()
+        tables = wl.ghost(np.asarray(ref.mu))
+        face = {}
+        for (axis, side), tab in tables.items():
+            if axis < wl.ndim:
+                nface = wl.ncell // wl.n[axis]
+                face[(axis, side)] = np.repeat(np.asarray(tab)[:, None], nface, axis=1)
+        wl.ghost_face = lambda mu, face=face: face
+        s = Solver(wl, precision=precision)
+        s.step(4)
+        b = s.state()
+        print(f"case {wl.name} {precision}: uniform face tables vs angle tables", flush=True)
+        for k in ("I", "T", "E", "F"):
+            assert np.array_equal(a[k], b[k]), k
+        # back to the angle tables, with a different table on one face in both
+        # runs: the two continue to agree
+        for (axis, side), tab in tables.items():
+            if axis < wl.ndim:
+                t2 = np.asarray(tab) * (1.5 if (axis, side) == (0, 0) else 1.0)
+                rt.rt_set_fixed_bc(s.ctx, axis, side, t2)
+                rt.rt_set_fixed_bc(ref.ctx, axis, side, t2)
+        ref.step(3)
+        s.step(3)
+        a, b = ref.state(), s.state()
+        ref.close()
+        s.close()
+        for k in ("I", "T", "E", "F"):
+            assert np.array_equal(a[k], b[k]), k
+
+
+def test_face_table_arguments():
+    from paper_1403_6126_amd import rt
+    from paper_1403_6126_amd.solver import Solver
+    bc = ((rt.RT_BC_FIXED, rt.RT_BC_VACUUM), (rt.RT_BC_PERIODIC, rt.RT_BC_PERIODIC),
+          (rt.RT_BC_PERIODIC, rt.RT_BC_PERIODIC))
+    wl = W.small_case(2, (8, 6), ("ls", 4), seed=85, bc=bc)
+    s = Solver(wl)
+    tab = np.zeros((len(s.mu), wl.ncell // wl.n[0]))
+    rt.rt_set_fixed_bc_face(s.ctx, 0, 0, tab)               # fixed face: accepted
+    for axis, side in ((0, 1), (1, 0), (2, 0), (-1, 0), (0, 2)):
+        with pytest.raises(rt.RTError) as e:
+            rt.rt_set_fixed_bc_face(s.ctx, axis, side, tab)  # not fixed, inactive or bad face
+        assert e.value.status == rt.RT_EINVAL
+    s.close()
