@@ -50,7 +50,8 @@ typedef enum rt_status {
   RT_EINVAL = -1,      /* invalid argument                                  */
   RT_ENOMEM = -2,      /* device or host allocation failed                  */
   RT_EDEVICE = -3,     /* HIP runtime error                                 */
-  RT_ECFL = -4,        /* dt violates sum_d C |mu_d| dt / dx_d <= 1         */
+  RT_ECFL = -4,        /* dt violates sum_d C |mu_d| dt / dx_d <= 1 (C the
+                          reduced speed when the context has one)           */
   RT_ENOCONV = -5,     /* Newton iteration of the temperature did not
                           converge, or gave a non-positive/non-finite T     */
   RT_EBADQUAD = -6,    /* weights do not sum to 1 or |n| != 1               */
@@ -107,6 +108,19 @@ typedef struct rt_params {
   double newton_rtol;  /* relative tolerance of the temperature Newton
                           iteration (e.g. 1e-14); <= 0 selects 1e-14        */
   int newton_maxit;    /* iteration limit (e.g. 64); <= 0 selects 64        */
+  double c_reduced;    /* reduced speed of light 0 < c_reduced <= c, or 0 for
+                          c itself (Section 6 combines the method with the
+                          reduced-speed-of-light approximation): the
+                          radiation advances at c_reduced (transport and
+                          both implicit source steps take the time step
+                          dt c_reduced/c, the CFL limit likewise) while the
+                          gas exchanges energy and momentum at the true
+                          rate (its changes are c/c_reduced times those of
+                          the radiation), so steady states are those of c
+                          and (c/c_reduced) Prat E_r + e_gas is conserved.
+                          The O(v/c) factors keep c.  RT_EUNSUPPORTED with
+                          RT_ESTIMATE_V (the velocity estimate is derived
+                          for one speed).                                    */
 } rt_params;
 
 typedef struct rt_fields { /* device arrays, [ncell] doubles unless noted */

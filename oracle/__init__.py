@@ -46,6 +46,7 @@ class _Problem(ct.Structure):
         ("estimate_v", ct.c_int), ("rtol", ct.c_double), ("maxit", ct.c_int),
         ("original", ct.c_int),
         ("ghost_face", (ct.POINTER(ct.c_double) * 2) * 3),
+        ("chat", ct.c_double),
     ]
 
 
@@ -97,7 +98,7 @@ class Problem:
 
     def __init__(self, wl, mu=None, w=None, estimate_v: bool = True,
                  rtol: float = 1e-14, maxit: int = 64, ghost=None, feedback: bool = False,
-                 original: bool = False):
+                 original: bool = False, c_reduced: float = 0.0):
         if mu is None:
             mu, w = angle_set(wl.quad)
         self.wl = wl
@@ -132,6 +133,14 @@ class Problem:
                 self._keep.append(g)
                 s.ghost_face[d][side] = _dp(g)
         s.C, s.P, s.gamma, s.R = wl.C, wl.P, wl.gamma, wl.R
+        # reduced speed of light (Section 6): the radiation advances at
+        # c_reduced, the gas exchanges energy and momentum at the true rate;
+        # the velocity estimate is derived for one speed and is not combined
+        # with it
+        if c_reduced and c_reduced != wl.C:
+            if not 0.0 < c_reduced < wl.C or estimate_v:
+                raise ValueError("c_reduced needs 0 < c_reduced < C and no velocity estimate")
+        s.chat = float(c_reduced)
         s.estimate_v = 1 if estimate_v else 0
         s.rtol = rtol
         s.maxit = maxit

@@ -217,10 +217,16 @@ static double cell_dF(const or_problem *p, double dt, const double *I,
   return dF;
 }
 
-void or_transport(const or_problem *p, double dt, const double *I,
+double or_radiation_dt(const or_problem *p, double dt) {
+  return p->chat > 0.0 ? dt * (p->chat / p->C) : dt;
+}
+
+void or_transport(const or_problem *p, double dt_gas, const double *I,
                   const double *J, const double *v, const double *sa,
                   const double *ss, double *dF) {
   const long long nc = ncell_of(p);
+  /* the transport is the radiation's: it advances at the (reduced) speed */
+  const double dt = or_radiation_dt(p, dt_gas);
 #pragma omp parallel for schedule(static) collapse(2)
   for (int m = 0; m < p->nang; ++m)
     for (int z = 0; z < p->n[2]; ++z)
@@ -285,6 +291,10 @@ int or_absorption_cell(const or_problem *p, double dt, double sa, double rho,
                        const double *u, const double *r, double Tn,
                        double *Iout, double *Tout) {
   const int N = p->nang;
+  /* the rows of the intensities advance by the radiation's time step, the
+   * row of the gas temperature by dt (the same unless the speed of light
+   * is reduced) */
+  const double dtr = or_radiation_dt(p, dt);
   const double C = p->C, P = p->P;
   const double cv = rho * p->R / (p->gamma - 1.0);
   const double uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
@@ -313,23 +323,23 @@ int or_absorption_cell(const or_problem *p, double dt, double sa, double rho,
     for (int m = 0; m < N; ++m) {
       const double rhs = C * sa * (T4pi - I[m]) + 3.0 * t[m] * sa * T4pi + t[m] * sa * I[m] -
                          sa * uu / C * sJ - sa / C * sK;
-      G[m] = I[m] - r[m] - dt * rhs;
+      G[m] = I[m] - r[m] - dtr * rhs;
     }
     const double rhsT = -8.0 * M_PI * P * sa * (sH - (uu * sJ + sK) / C) -
                         P * C * (1.0 - uu / (C * C)) * sa * (T * T * T * T - FOURPI * sJ);
     const double GT = cv * (T - Tn) - dt * rhsT;
 
-    /* Jacobian entries:
+    /* Jacobian entries (dtr the radiation's step, dt the gas's):
      *   dG_m/dI_l = delta_ml D_m + kappa g_l W_l,
-     *     D_m = 1 + dt sa (C - t_m), kappa = dt sa / C, g_l = u.u + t_l^2
-     *   dG_m/dT   = -e_m T^3/pi,  e_m = dt sa (C + 3 t_m)
+     *     D_m = 1 + dtr sa (C - t_m), kappa = dtr sa / C, g_l = u.u + t_l^2
+     *   dG_m/dT   = -e_m T^3/pi,  e_m = dtr sa (C + 3 t_m)
      *   dG_T/dI_l = gT_l = dt [8pi P sa (t_l - g_l/C) - 4pi P C (1-u.u/C^2) sa] W_l
      *   dG_T/dT   = c_v + 4 dt P C (1 - u.u/C^2) sa T^3 */
-    const double kap = dt * sa / C;
+    const double kap = dtr * sa / C;
     const double T3pi = T * T * T / M_PI;
     const int Nn = N - 1;
-    const double DN = 1.0 + dt * sa * (C - t[Nn]);
-    const double eN = dt * sa * (C + 3.0 * t[Nn]);
+    const double DN = 1.0 + dtr * sa * (C - t[Nn]);
+    const double eN = dtr * sa * (C + 3.0 * t[Nn]);
     /* rows m != N minus row N:
      *   D_m dI_m - D_N dI_N - (e_m - e_N) T^3/pi dT = -(G_m - G_N) */
     for (int m = 0; m < N; ++m) {
@@ -339,8 +349,8 @@ int or_absorption_cell(const or_problem *p, double dt, double sa, double rho,
         dIc[m] = 0.0;
         continue;
       }
-      const double Dm = 1.0 + dt * sa * (C - t[m]);
-      const double em = dt * sa * (C + 3.0 * t[m]);
+      const double Dm = 1.0 + dtr * sa * (C - t[m]);
+      const double em = dtr * sa * (C + 3.0 * t[m]);
       dIa[m] = DN / Dm;
       dIb[m] = (em - eN) * T3pi / Dm;
       dIc[m] = -(G[m] - G[Nn]) / Dm;
@@ -395,9 +405,10 @@ int or_absorption_cell(const or_problem *p, double dt, double sa, double rho,
  *   c_m = -3 dt ss n_m.u.
  * Solved here by plain Gaussian elimination with partial pivoting of the
  * dense matrix (the paper's analytic LU reaches the same solution). */
-int or_scattering_cell(const or_problem *p, double dt, double ss,
+int or_scattering_cell(const or_problem *p, double dt_gas, double ss,
                        const double *u, const double *r, double *Iout) {
   const int N = p->nang;
+  const double dt = or_radiation_dt(p, dt_gas); /* a radiation-only step */
   if (ss == 0.0) {
     /* no scattering: M_s = diag(1/W_m), so I'_m = r_m */
     for (int m = 0; m < N; ++m) Iout[m] = r[m];
@@ -499,9 +510,12 @@ static int source_cell(const or_problem *p, double dt, double rho, double sa,
   const double cv = rho * p->R / (p->gamma - 1.0);
   const double dET = cv * (T4 - Tn);
   double m0sq = 0, m1sq = 0;
+  /* the gas gains the momentum the radiation loses, at the true rate: C/chat
+   * times the radiation's change with a reduced speed of light */
+  const double gas = p->chat > 0.0 ? p->C / p->chat : 1.0;
   for (int k = 0; k < 3; ++k) {
-    const double d4 = -(FOURPI * p->P / p->C) * (H4[k] - Hr4[k]);
-    const double d5 = -(FOURPI * p->P / p->C) * (H5[k] - Hr5[k]);
+    const double d4 = -gas * (FOURPI * p->P / p->C) * (H4[k] - Hr4[k]);
+    const double d5 = -gas * (FOURPI * p->P / p->C) * (H5[k] - Hr5[k]);
     dMom[k] = d4 + d5;
     const double m0 = rho * v[k];
     m0sq += m0 * m0;

@@ -50,12 +50,21 @@ typedef struct or_problem {
                             its angle table; nface = cells of the face, in
                             order of the two other axes, lower one fastest
                             (beams through part of a face, Section 5.4)    */
+  double chat;           /* reduced speed of light (0: C itself): the
+                            radiation advances at chat, the gas exchanges
+                            energy and momentum at the true rate (the
+                            reduced-speed-of-light approximation that
+                            Section 6 combines with the method)             */
 } or_problem;
 
 /* Angular quadrature of I (Section 3): E = 4pi sum W I, F_k = 4pi sum W mu_k I,
  * P_ij = 4pi sum W mu_i mu_j I.  Any output pointer may be NULL. */
 void or_moments(const or_problem *p, const double *I, double *E, double *F,
                 double *Pr);
+
+/* Time step of the radiation for a step dt of the gas: dt chat/C with a
+ * reduced speed of light chat, else dt. */
+double or_radiation_dt(const or_problem *p, double dt);
 
 /* Transport increment Delta F (Section 4.2) for every angle and cell, from
  * the intensities I and the mean intensity J (both at time n). */

@@ -191,14 +191,26 @@ long long ctx_step_blocks(const rt_ctx *c) {
 
 int ctx_storage_bytes(const rt_ctx *c) { return c->p.precision == RT_FP32_MIXED ? 4 : 8; }
 
+// The speed at which the radiation advances: c, or the reduced speed.
+double radiation_speed(const rt_ctx *c) {
+  return c->p.c_reduced > 0.0 ? c->p.c_reduced : c->p.c;
+}
+
 int ctx_check_dt(const rt_ctx *c, double dt) {
   if (!(dt > 0.0) || !std::isfinite(dt)) return RT_EINVAL;
-  if (c->p.c * dt * c->cfl_sum > 1.0 + 1e-12) return RT_ECFL;
+  if (radiation_speed(c) * dt * c->cfl_sum > 1.0 + 1e-12) return RT_ECFL;
   return RT_OK;
 }
 
-void ctx_fill_args(const rt_ctx *c, double dt, const rt_fields *f, StepArgs &a) {
+void ctx_fill_args(const rt_ctx *c, double dt_call, const rt_fields *f, StepArgs &a) {
   std::memset(&a, 0, sizeof(a));
+  // with the reduced speed of light the radiation takes the step dt c_r/C in
+  // every one of its terms (transport and sources); the gas keeps the true
+  // coupling through a heat capacity (and, in the outputs, momentum) scaled
+  // by c_r/C, which gives the temperature of the true-rate gas equation
+  const double sc = radiation_speed(c) / c->p.c;
+  const double dt = dt_call * sc;
+  a.gasfac = 1.0 / sc;
   a.ndim = c->g.ndim;
   a.ivfac = (c->p.flags & RT_ORIGINAL_TRANSPORT) ? 0.0 : 3.0;
   for (int d = 0; d < 3; ++d) {
@@ -218,7 +230,7 @@ void ctx_fill_args(const rt_ctx *c, double dt, const rt_fields *f, StepArgs &a) 
   a.C = c->p.c;
   a.invC = 1.0 / c->p.c;
   a.P = c->p.prat;
-  a.cvfac = c->p.r_ideal / (c->p.gamma - 1.0);
+  a.cvfac = c->p.r_ideal / (c->p.gamma - 1.0) * sc;
   double vol = 1.0;
   for (int d = 0; d < c->g.ndim; ++d) vol *= c->g.dx[d];
   a.vol = vol;
@@ -275,6 +287,9 @@ int ctx_init_host(const rt_grid *g, const rt_angles *an, const rt_params *p, rt_
   if (!(p->c > 0.0) || !(p->prat >= 0.0) || !(p->gamma > 1.0) || !(p->r_ideal > 0.0))
     return RT_EINVAL;
   if (p->precision != RT_FP64 && p->precision != RT_FP32_MIXED) return RT_EINVAL;
+  if (!(p->c_reduced >= 0.0) || p->c_reduced > p->c) return RT_EINVAL;
+  if (p->c_reduced > 0.0 && p->c_reduced < p->c && (p->flags & RT_ESTIMATE_V))
+    return RT_EUNSUPPORTED;
 
   c->g = *g;
   c->p = *p;

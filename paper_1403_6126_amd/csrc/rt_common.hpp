@@ -22,7 +22,8 @@ struct StepArgs {
   int ndim, n[3], ncell, nang;
   int bc[3][2];
   int stride[3];
-  double dt, C, invC, P, cvfac;  // cvfac = R/(gamma - 1)
+  double dt, C, invC, P, cvfac;  // cvfac = R/(gamma - 1) (times c_r/C, below)
+  double gasfac;                 // C/c_r: gas change per radiation change (1 at c_r = C)
   double dt_dx[3];               // dt / dx_d
   double dl10[3];                // 10 dx_d (transport speed factor alpha; 0 gives alpha = 1)
   double ivfac;                  // 3 in IV = 3 n.v J (0: no IV split, I~ = I)

@@ -383,15 +383,16 @@ __global__ __launch_bounds__(kBlock) void k_step(StepArgs p) {
 
     // Step 7 source terms: momentum from photon momentum conservation,
     // kinetic energy from the fixed gas velocity, internal energy from T'.
-    const double f4 = kFourPi * P / C;
-    const double dm0 = -(P / C) * mom[1] + f4 * M0;
-    const double dm1 = -(P / C) * mom[2] + f4 * M1;
-    const double dm2 = -(P / C) * mom[3] + f4 * M2;
+    // (gasfac: C over the reduced speed of light, 1 without one)
+    const double f4 = kFourPi * P / C, gf = p.gasfac;
+    const double dm0 = gf * (-(P / C) * mom[1] + f4 * M0);
+    const double dm1 = gf * (-(P / C) * mom[2] + f4 * M1);
+    const double dm2 = gf * (-(P / C) * mom[3] + f4 * M2);
     const double m0 = rho * v0, m1 = rho * v1, m2 = rho * v2;
     const double ek = (((m0 + dm0) * (m0 + dm0) + (m1 + dm1) * (m1 + dm1) + (m2 + dm2) * (m2 + dm2)) -
                        (m0 * m0 + m1 * m1 + m2 * m2)) /
                       (2.0 * rho);
-    const double dET = cv * (T - Tn);
+    const double dET = cv * gf * (T - Tn);
     const double deg = dET + ek;
     p.T[c] = T;
     if (p.dEgas) p.dEgas[c] = (p.accumulate ? p.dEgas[c] : 0.0) + deg;
@@ -402,7 +403,7 @@ __global__ __launch_bounds__(kBlock) void k_step(StepArgs p) {
     }
     const double vol = p.vol;
     tot[0] = P * mom[0] * vol;
-    tot[1] = cv * T * vol;
+    tot[1] = cv * gf * T * vol;
     tot[2] = deg * vol;
     tot[3] = ek * vol;
     tot[4] = dm0 * vol;

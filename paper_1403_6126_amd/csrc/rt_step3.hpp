@@ -478,16 +478,19 @@ __device__ __forceinline__ void step3_tile(const StepArgs &p, int blk, int G, St
   for (int r = 0; r < 10; ++r) mo[r] *= kFourPi;
 
   // ------------------------------------------------ Step 7 and outputs
-  const double f4 = kFourPi * P / C;
-  const double dm0 = -(P / C) * mo[1] + f4 * Sb[8];
-  const double dm1 = -(P / C) * mo[2] + f4 * Sb[9];
-  const double dm2 = -(P / C) * mo[3] + f4 * Sb[10];
+  // the gas changes: gasfac (C over the reduced speed, 1 without one) times
+  // the momentum the radiation loses, and the true heat capacity
+  const double f4 = kFourPi * P / C, gf = p.gasfac;
+  const double dm0 = gf * (-(P / C) * mo[1] + f4 * Sb[8]);
+  const double dm1 = gf * (-(P / C) * mo[2] + f4 * Sb[9]);
+  const double dm2 = gf * (-(P / C) * mo[3] + f4 * Sb[10]);
   const double mm0 = rho * v0, mm1 = rho * v1, mm2 = rho * v2;
   const double ek =
       (((mm0 + dm0) * (mm0 + dm0) + (mm1 + dm1) * (mm1 + dm1) + (mm2 + dm2) * (mm2 + dm2)) -
        (mm0 * mm0 + mm1 * mm1 + mm2 * mm2)) /
       (2.0 * rho);
-  const double deg = cv * (T - Tn) + ek;
+  const double cvg = cv * gf;
+  const double deg = cvg * (T - Tn) + ek;
   // gas feedback (rho fixed): the momentum change of the step moves the flow;
   // 3 v J of the new state, used by the next step's IV, takes the new v
   const double vn0 = p.feedback ? v0 + dm0 / rho : v0;
@@ -555,7 +558,7 @@ __device__ __forceinline__ void step3_tile(const StepArgs &p, int blk, int G, St
     const double vol = p.vol;
     const bool on = act;
     tot[0] = on ? P * mo[0] * vol : 0.0;
-    tot[1] = on ? cv * T * vol : 0.0;
+    tot[1] = on ? cvg * T * vol : 0.0;
     tot[2] = on ? deg * vol : 0.0;
     tot[3] = on ? ek * vol : 0.0;
     tot[4] = on ? dm0 * vol : 0.0;

@@ -50,7 +50,8 @@ class rt_angles(ct.Structure):
 class rt_params(ct.Structure):
     _fields_ = [("c", ct.c_double), ("prat", ct.c_double), ("gamma", ct.c_double),
                 ("r_ideal", ct.c_double), ("precision", ct.c_int), ("flags", ct.c_uint),
-                ("newton_rtol", ct.c_double), ("newton_maxit", ct.c_int)]
+                ("newton_rtol", ct.c_double), ("newton_maxit", ct.c_int),
+                ("c_reduced", ct.c_double)]
 
 
 class rt_fields(ct.Structure):
@@ -206,8 +207,9 @@ def make_grid(ndim, n, dx, bc) -> rt_grid:
 
 
 def make_params(c, prat, gamma, r_ideal, precision=RT_FP64, flags=RT_ESTIMATE_V,
-                newton_rtol=1e-14, newton_maxit=64) -> rt_params:
-    return rt_params(c, prat, gamma, r_ideal, precision, flags, newton_rtol, newton_maxit)
+                newton_rtol=1e-14, newton_maxit=64, c_reduced=0.0) -> rt_params:
+    return rt_params(c, prat, gamma, r_ideal, precision, flags, newton_rtol, newton_maxit,
+                     c_reduced)
 
 
 def rt_create(grid: rt_grid, mu: np.ndarray, w: np.ndarray, params: rt_params) -> int:
