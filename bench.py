@@ -189,8 +189,9 @@ def main():
                          "(counter calibration) and exit")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); multi-GPU runs "
-              "are not part of this build", file=sys.stderr)
+        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}): the library "
+              "has no multi-GPU path (the domain decomposition it would use is a design, "
+              "not code)", file=sys.stderr)
         sys.exit(2)
 
     import torch

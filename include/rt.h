@@ -56,7 +56,7 @@ typedef enum rt_status {
                           converge, or gave a non-positive/non-finite T     */
   RT_EBADQUAD = -6,    /* weights do not sum to 1 or |n| != 1               */
   RT_ESTATE = -7,      /* call order violated (e.g. no intensity bound)     */
-  RT_EUNSUPPORTED = -8 /* valid request this build does not support         */
+  RT_EUNSUPPORTED = -8 /* valid request the library does not support        */
 } rt_status;
 
 enum { RT_BC_PERIODIC = 0, RT_BC_FIXED = 1, RT_BC_COPY = 2, RT_BC_VACUUM = 3 };
