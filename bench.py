@@ -89,14 +89,17 @@ def run_gpu(wl, precision: str, steps: int, warmup: int):
                 grid_blocks=info.grid_blocks, block_threads=info.block_threads)
 
 
-def cpu_baseline(wl, budget_s: float = 12.0, batch: int = 65536, seed: int = 0):
+def cpu_baseline(wl, budget_s: float = 12.0, batch: int = 65536, seed: int = 0,
+                 threads: int = 0):
     """The CPU oracle (as it stands) on a bounded sample of the same workload:
     one step evaluated on batches of random cells of the 128^3 box until the
-    time budget is spent."""
+    time budget is spent, on all host threads or on `threads` of them."""
     import numpy as np
 
     import oracle
 
+    if threads > 0:
+        oracle.set_threads(threads)
     prob = oracle.Problem(wl)
     I = wl.init(prob.mu)
     rng = np.random.default_rng(seed)
@@ -176,6 +179,10 @@ def main():
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=12.0)
+    ap.add_argument("--cpu-threads", type=int, default=0,
+                    help="threads of the CPU-baseline leg (0: all host threads)")
+    ap.add_argument("--only-cpu", action="store_true",
+                    help="run the CPU-baseline leg alone (no GPU) and print its JSON")
     ap.add_argument("--only", choices=["fp64", "mixed"], default=None,
                     help="profiling: run one precision only and print its timing")
     ap.add_argument("--serve-requests", type=int, default=200,
@@ -193,6 +200,11 @@ def main():
               "has no multi-GPU path (the domain decomposition it would use is a design, "
               "not code)", file=sys.stderr)
         sys.exit(2)
+    if args.only_cpu:
+        import workloads as W
+        print(json.dumps(cpu_baseline(W.config2(nper=args.nper), args.cpu_budget,
+                                      threads=args.cpu_threads)), flush=True)
+        return
 
     import torch
 
@@ -246,7 +258,7 @@ def main():
     cpu = None
     if not args.no_cpu_baseline:
         print("bench: cpu baseline (oracle)", file=sys.stderr, flush=True)
-        cpu = cpu_baseline(wl, args.cpu_budget)
+        cpu = cpu_baseline(wl, args.cpu_budget, threads=args.cpu_threads)
     line = {
         "metric": METRIC,
         "value": r64["value"],

@@ -78,6 +78,8 @@ def lib():
         L.or_step_cells.restype = ct.c_int
         L.or_totals.argtypes = [pp, dp, dp, dp, dp, dp, dp, dp, dp, dp]
         L.or_threads.restype = ct.c_int
+        L.or_set_threads.argtypes = [ct.c_int]
+        L.or_set_threads.restype = None
         _lib = L
     return _lib
 
@@ -299,3 +301,8 @@ def step_cells(prob: Problem, I, T, cells, dt=None):
 
 def threads() -> int:
     return int(lib().or_threads())
+
+
+def set_threads(n: int) -> None:
+    """Number of OpenMP threads of the later oracle calls."""
+    lib().or_set_threads(int(n))

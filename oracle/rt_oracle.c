@@ -25,6 +25,14 @@ int or_threads(void) {
 #endif
 }
 
+void or_set_threads(int n) {
+#ifdef _OPENMP
+  if (n >= 1) omp_set_num_threads(n);
+#else
+  (void)n;
+#endif
+}
+
 static long long ncell_of(const or_problem *p) {
   return (long long)p->n[0] * p->n[1] * p->n[2];
 }

@@ -125,6 +125,9 @@ void or_totals(const or_problem *p, const double *rho, const double *T,
 /* Number of OpenMP threads the oracle uses (1 when built without OpenMP). */
 int or_threads(void);
 
+/* Sets the number of OpenMP threads of the later calls (n >= 1). */
+void or_set_threads(int n);
+
 #ifdef __cplusplus
 }
 #endif
