@@ -213,13 +213,23 @@ def main():
     assert torch.cuda.is_available(), "no GPU visible"
     torch.cuda.set_device(0)
     if args.copy_probe > 0:
+        # a plain device-to-device copy: the counter calibration, and the
+        # measured bandwidth the step kernels can be set against
         n = int(args.copy_probe * (1 << 30)) // 8
         src = torch.ones(n, dtype=torch.float64, device="cuda")
         dst = torch.empty_like(src)
-        for _ in range(args.steps):
+        for _ in range(2):
             dst.copy_(src)
         torch.cuda.synchronize()
-        print(json.dumps({"copy_probe_bytes_each_way": 8 * n, "launches": args.steps}))
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(args.steps):
+            dst.copy_(src)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / args.steps
+        print(json.dumps({"copy_probe_bytes_each_way": 8 * n, "launches": args.steps,
+                          "ms_per_copy": ms, "read_plus_write_gbs": 2 * 8 * n / ms / 1e6}))
         return
     if args.only_serve:
         print(json.dumps(serving(args.serve_requests, args.serve_load, args.serve_warm)),
