@@ -65,7 +65,9 @@ def _grid():
     return rt.make_grid(3, (4, 4, 4), (0.25, 0.25, 0.25), ((0, 0),) * 3)
 
 
-@pytest.mark.parametrize("case", ["weights", "norm", "ndim", "bc", "c", "gamma"])
+@pytest.mark.parametrize("case", ["weights", "norm", "ndim", "bc", "c", "gamma", "cells",
+                                  "angles", "c_reduced_above_c", "c_reduced_negative",
+                                  "c_reduced_with_estimate"])
 def test_create_validation_before_device(case):
     mu, w = rt.rt_quadrature(rt.RT_QUAD_LEVEL_SYMMETRIC, 4)
     g = _grid()
@@ -85,6 +87,21 @@ def test_create_validation_before_device(case):
         p.c = 0.0
     elif case == "gamma":
         p.gamma = 1.0
+    elif case == "cells":                # cell indices are 32-bit
+        g = rt.make_grid(3, (2048, 2048, 1024), (1.0, 1.0, 1.0), ((0, 0),) * 3)
+        expect = rt.RT_EUNSUPPORTED
+    elif case == "angles":               # more than RT_MAX_ANGLES directions
+        n = 1026
+        phi = np.arange(n) * 2 * np.pi / n
+        mu = np.stack([np.cos(phi), np.sin(phi), np.zeros(n)], axis=1)
+        w = np.full(n, 1.0 / n)
+    elif case == "c_reduced_above_c":
+        p = rt.make_params(1.0, 1.0, 5 / 3, 1.0, flags=0, c_reduced=1.5)
+    elif case == "c_reduced_negative":
+        p = rt.make_params(1.0, 1.0, 5 / 3, 1.0, flags=0, c_reduced=-0.5)
+    elif case == "c_reduced_with_estimate":
+        p = rt.make_params(1.0, 1.0, 5 / 3, 1.0, flags=rt.RT_ESTIMATE_V, c_reduced=0.5)
+        expect = rt.RT_EUNSUPPORTED
     with pytest.raises(rt.RTError) as ei:
         rt.rt_create(g, mu, w, p)
     assert ei.value.status == expect
