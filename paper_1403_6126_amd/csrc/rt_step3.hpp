@@ -156,6 +156,20 @@ __device__ __forceinline__ void waves_reduce(double (&x)[NV], double *buf, doubl
 #ifndef RT_UNROLL_F32
 #define RT_UNROLL_F32 1
 #endif
+// The new intensities and the per-cell outputs are written once and not read
+// again by the step: with RT_STREAM_STORES they bypass the caches as
+// non-temporal stores, leaving L2 to the stencil reuse and the spill.
+#ifndef RT_STREAM_STORES
+#define RT_STREAM_STORES 1
+#endif
+template <typename T>
+__device__ __forceinline__ void stream_store(T *p, T v) {
+  if constexpr (RT_STREAM_STORES)
+    __builtin_nontemporal_store(v, p);
+  else
+    *p = v;
+}
+
 // Slots whose plane reads are in flight ahead of the transport arithmetic
 // (FP64 storage: one, as registers allow).
 #ifndef RT_PREFETCH_F64
@@ -459,7 +473,7 @@ __device__ __forceinline__ void step3_tile(const StepArgs &p, int blk, int G, St
     const A cm = A(-3) * dss * t;
     // I' = invaw (p - s1 - c s2) + invD invaw (e X - kappa Q)
     const S Inew = S(D * rDa * (pk[k] - As1 - cm * As2) + rDa * (e * AX - AkQ));
-    if (act) Iout[(size_t)m * N + c] = Inew;
+    if (act) stream_store(&Iout[(size_t)m * N + c], Inew);
     const double Iw = double(Inew) * p.w[m];
     mo[0] += Iw;
     mo[1] += d0 * Iw;
@@ -543,7 +557,7 @@ __device__ __forceinline__ void step3_tile(const StepArgs &p, int blk, int G, St
         val = mo[f - 18];
         dst = p.oP + (size_t)(f - 22) * N;
       }
-      dst[c] = val;
+      stream_store(&dst[c], val);
     }
     // gas feedback: the new velocity (every wave has read this cell's v
     // before the reductions above)
