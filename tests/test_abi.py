@@ -128,3 +128,19 @@ def test_serve_config_validation_before_device(field, value):
     with pytest.raises(rt.RTError) as ei:
         rt.rt_serve_create(**cfg)
     assert ei.value.status == rt.RT_EINVAL
+
+
+def test_headers_are_plain_c(tmp_path):
+    """The boundary headers compile as strict C99 (plain pointers and sizes,
+    no C++ or torch types), and every declared function is callable from C."""
+    src = tmp_path / "use.c"
+    src.write_text('#include "rt.h"\n#include "rt_serve.h"\n'
+                   "int use(void) {\n"
+                   "  rt_params p; rt_request r; rt_serve_config s;\n"
+                   "  (void)p; (void)r; (void)s;\n"
+                   "  return (int)sizeof(rt_fields) + (int)sizeof(rt_out);\n"
+                   "}\n")
+    r = subprocess.run(["gcc", "-std=c99", "-pedantic", "-Wall", "-Wextra", "-Werror",
+                        "-I", os.path.join(ROOT, "include"), "-c", str(src), "-o",
+                        str(tmp_path / "use.o")], capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr
