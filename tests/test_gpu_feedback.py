@@ -6,6 +6,7 @@ import numpy as np
 import pytest
 
 import workloads as W
+from golden_values import golden
 
 pytestmark = pytest.mark.gpu
 
@@ -56,8 +57,10 @@ def test_moving_medium(sa, ss, precision):
     st = _run(wl, 60, precision)
     E, Pxx, Pyy, Fx = st["E"].mean(), st["P"][0].mean(), st["P"][1].mean(), st["F"][0].mean()
     v = st["v"][0].mean()
-    # the paper's equilibrium: f_xx ~ 0.37, f_yy ~ 0.315, comoving flux zero
-    assert abs(Pxx / E - 0.37) <= 0.005 and abs(Pyy / E - 0.315) <= 0.005
+    # the paper's equilibrium (printed to two digits), comoving flux zero
+    g = golden("sec5_2_moving_medium.json")
+    assert abs(Pxx / E - g["f_xx_equilibrium_about"]) <= 0.005
+    assert abs(Pyy / E - g["f_yy_equilibrium_about"]) <= 0.005
     assert abs(Fx - v * (E + Pxx) / wl.C) <= 1e-5 * Fx
     assert v < 3.0
 

@@ -13,6 +13,7 @@ import numpy as np
 
 import workloads as W
 from rays import beam_stats
+from golden_values import golden
 
 
 def _run(nx):
@@ -46,11 +47,17 @@ def test_crossing_beams_oracle_pins():
 
 
 def test_crossing_beam_windows():
+    s = golden("sec5_4_crossing_beams.json")
+    full = W.crossing_beams()
+    assert [full.n[0], full.n[1]] == s["resolutions"][0]
+    assert (full.n[0] * full.dx[0], full.n[1] * full.dx[1]) == tuple(s["box"])
+    assert full.bc[0] == (W.BC_PERIODIC, W.BC_PERIODIC) and np.all(full.sigma_a == 0.0)
+    assert np.all(full.sigma_s == s["sigma_s"])
     wl = W.crossing_beams(nx=32, ny=128)
     mu = np.asarray(wl.quad[1])
     R, L = wl.meta["beams"]
-    assert np.degrees(np.arctan2(mu[R, 1], mu[R, 0])) == 45.0
-    assert np.degrees(np.arctan2(mu[L, 1], mu[L, 0])) == 135.0
+    assert [np.degrees(np.arctan2(mu[m, 1], mu[m, 0])) for m in (R, L)] == \
+        s["beam_angles_deg_from_plus_x"]
     g = wl.ghost_face(mu)[(1, 0)]
     assert g.shape == (4, 32)
     assert g[R].sum() == 4 and g[L].sum() == 4           # 1/8 of the face each

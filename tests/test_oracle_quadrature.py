@@ -3,6 +3,7 @@ import numpy as np
 import pytest
 
 from oracle.quadrature import gauss_legendre, level_symmetric
+from golden_values import golden
 
 ORDERS = [2, 4, 6, 8, 10, 12, 14, 16]
 COUNTS = {2: 8, 4: 24, 6: 48, 8: 80, 10: 120, 12: 168, 14: 224, 16: 288}
@@ -50,7 +51,8 @@ def test_s4_matches_paper_printed_cosines():
     mu, w = level_symmetric(4)
     vals = np.unique(np.round(np.abs(mu), 12))
     assert np.allclose(vals, [1 / 3, np.sqrt(7) / 3], atol=1e-12)
-    assert abs(vals[0] - 0.333) < 5e-4 and abs(vals[1] - 0.882) < 5e-4
+    printed = golden("sec5_2_moving_medium.json")["mu_z_of_the_two_ray_families"]
+    assert np.allclose(vals, printed, atol=5e-4)                   # three printed digits
     assert np.allclose(w, 1 / 24)
 
 

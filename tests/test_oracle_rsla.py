@@ -17,6 +17,7 @@ import numpy as np
 import pytest
 
 import workloads as W
+from golden_values import golden
 
 FOUR_PI = 4.0 * np.pi
 
@@ -44,8 +45,11 @@ def _root(a, b, rhs):
     return max(r.real for r in roots if abs(r.imag) < 1e-9 * abs(r) and r.real > 0)
 
 
-@pytest.mark.parametrize("sa", [1.0, 100.0])
-@pytest.mark.parametrize("E0,T0", [(100.0, 1.0), (1.0, 100.0)])
+_S51 = golden("sec5_1_thermal_equilibrium.json")
+
+
+@pytest.mark.parametrize("sa", _S51["sigma_a"])
+@pytest.mark.parametrize("E0,T0", [(s["E_r"], s["T4"] ** 0.25) for s in _S51["initial_states"]])
 def test_reduced_speed_relaxation_closed_form(orc, sa, E0, T0):
     cr = 1.0
     wl, st = _uniform(orc, sa, E0, T0, cr)

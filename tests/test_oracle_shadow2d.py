@@ -13,6 +13,7 @@ import pytest
 
 import workloads as W
 from rays import classify, ray_energy
+from golden_values import golden
 
 FOUR_PI = 4.0 * np.pi
 
@@ -44,16 +45,34 @@ def test_shadow2d_oracle_converges_to_ray_solution():
     assert errs[64] < 0.6 * errs[32]
 
 
-def test_shadow2d_beam_tables():
-    """The beams enter where Section 5.8 puts them, at +-14 degrees."""
-    wl = W.shadow2d(nx=32, ny=16)
+def test_shadow2d_setup_is_the_papers():
+    """The workload is the printed setup of Section 5.8: box, resolution,
+    Crat, cloud, and the beams where the paper puts them."""
+    s = golden("sec5_8_shadow.json")
+    wl = W.shadow2d()
+    assert (wl.n[0], wl.n[1]) == tuple(s["resolution"]) and wl.C == s["Crat"]
+    assert wl.meta["box"] == tuple(tuple(b) for b in s["box"])
+    assert wl.dx[0] * wl.n[0] == pytest.approx(s["box"][0][1] - s["box"][0][0])
+    assert wl.dx[1] * wl.n[1] == pytest.approx(s["box"][1][1] - s["box"][1][0])
+    assert W.shadow_density(0.0, 0.0) == pytest.approx(
+        s["rho0"] + (s["rho1_over_rho0"] - 1.0) * s["rho0"] / (1.0 + np.exp(-10.0)))
+    assert W.shadow_density(s["ellipse_a"], 0.0) == pytest.approx(
+        s["rho0"] + 0.5 * (s["rho1_over_rho0"] - 1.0) * s["rho0"])   # r = 1 on the ellipse
+    assert W.shadow_density(0.0, s["ellipse_b"]) == pytest.approx(
+        s["rho0"] + 0.5 * (s["rho1_over_rho0"] - 1.0) * s["rho0"])
+    far = W.shadow_density(0.45, 0.25)
+    assert far == pytest.approx(s["rho0"]) and wl.T.max() == pytest.approx(1.0 / s["rho0"])
     mu = np.asarray(wl.quad[1])
     up, down = wl.meta["beams"]
-    assert np.degrees(np.arctan2(mu[up, 1], mu[up, 0])) == pytest.approx(14.0, abs=1e-9)
-    assert np.degrees(np.arctan2(mu[down, 1], mu[down, 0])) == pytest.approx(-14.0, abs=1e-9)
+    ang = {"up": np.degrees(np.arctan2(mu[up, 1], mu[up, 0])),
+           "down": np.degrees(np.arctan2(mu[down, 1], mu[down, 0]))}
+    assert sorted(s["beam_angles_deg"]["left"]) == pytest.approx(sorted(ang.values()), abs=1e-9)
+    assert s["beam_angles_deg"]["bottom"] == pytest.approx([ang["up"]], abs=1e-9)
+    assert s["beam_angles_deg"]["top"] == pytest.approx([ang["down"]], abs=1e-9)
     g = wl.ghost(mu)
     bg = 1.0 / FOUR_PI
-    assert g[(0, 0)][up] == g[(0, 0)][down] == 103.13
-    assert g[(1, 0)][up] == 103.13 and g[(1, 0)][down] == bg
-    assert g[(1, 1)][down] == 103.13 and g[(1, 1)][up] == bg
+    beam = s["beam_intensity"]
+    assert g[(0, 0)][up] == g[(0, 0)][down] == beam
+    assert g[(1, 0)][up] == beam and g[(1, 0)][down] == bg
+    assert g[(1, 1)][down] == beam and g[(1, 1)][up] == bg
     assert np.sum(np.asarray(wl.quad[2])) == pytest.approx(1.0, abs=1e-15)
