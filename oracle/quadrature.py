@@ -18,6 +18,12 @@ weights here sum to one (J is the mean intensity).
   graded order (degree, then single-axis powers first), keeping the first
   independent conditions.
 
+Parity unpinned: the paper cites, but does not print, the tables of its
+level-symmetric weights, so these weights are not checked against the
+paper's sets; what is pinned is that they reproduce the printed cosines and
+the exact sphere averages (sum W = 1, sum W n = 0, sum W n n = 1/3 delta and
+the higher even moments the conditions above impose).
+
 Canonical order (shared with the GPU library so tables can be compared
 entry by entry): octant o = 0..7 with signs (-1 if o&1, -1 if o&2, -1 if
 o&4) on (x, y, z); inside an octant, points by ascending i then j.
