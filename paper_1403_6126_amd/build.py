@@ -26,6 +26,15 @@ HIPCC_FLAGS = [
 ]
 
 
+# Per-file additions: the FP64 step kernels schedule with the iterative
+# occupancy-preserving strategy of the AMDGPU backend, which measured about
+# 2 % faster on the FP64 fused step (latency-bound at four waves per SIMD);
+# the FP32 kernels keep the default.
+EXTRA_FLAGS = {
+    "rt_kernels_f64.hip": ["-mllvm", "-amdgpu-sched-strategy=iterative-maxocc"],
+}
+
+
 def _hipcc() -> str:
     return os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
@@ -36,7 +45,8 @@ def build(verbose: bool = False, jobs: int = 8) -> str:
 
     def compile_one(name: str) -> str:
         obj = os.path.join(OBJDIR, name + ".o")
-        cmd = [_hipcc(), *HIPCC_FLAGS, *inc, "-c", os.path.join(CSRC, name), "-o", obj]
+        cmd = [_hipcc(), *HIPCC_FLAGS, *EXTRA_FLAGS.get(name, []), *inc, "-c",
+               os.path.join(CSRC, name), "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
         subprocess.run(cmd, check=True)
