@@ -47,6 +47,7 @@ class _Problem(ct.Structure):
         ("original", ct.c_int),
         ("ghost_face", (ct.POINTER(ct.c_double) * 2) * 3),
         ("chat", ct.c_double),
+        ("second_order", ct.c_int),
     ]
 
 
@@ -100,7 +101,8 @@ class Problem:
 
     def __init__(self, wl, mu=None, w=None, estimate_v: bool = True,
                  rtol: float = 1e-14, maxit: int = 64, ghost=None, feedback: bool = False,
-                 original: bool = False, c_reduced: float = 0.0):
+                 original: bool = False, c_reduced: float = 0.0,
+                 second_order: bool = False):
         if mu is None:
             mu, w = angle_set(wl.quad)
         self.wl = wl
@@ -149,6 +151,9 @@ class Problem:
         # the original transport (Section 4.2 before the reduced speed and the
         # IV split; the Section 5.5 comparison)
         s.original = 1 if original else 0
+        # the absorption step solved twice, the second time at the
+        # time-centred velocity (Section 4.3, second order in time)
+        s.second_order = 1 if second_order else 0
         self.s = s
         # gas feedback (Section 4.1 Step 7 with rho held fixed): after every
         # step the gas momentum change of the step moves the velocity,

@@ -491,7 +491,17 @@ int or_scattering_cell(const or_problem *p, double dt_gas, double ss,
  *     there); the 4pi converts H to F_r so that rho v + P F_r/C is
  *     conserved.  Step 5 likewise with r5.
  *   Gas internal energy change c_v (T' - T^n), c_v = rho R/(gamma - 1).
- *   Kinetic energy change ((rho v^n + d(rho v))^2 - (rho v^n)^2)/(2 rho). */
+ *   Kinetic energy change ((rho v^n + d(rho v))^2 - (rho v^n)^2)/(2 rho).
+ * Second order in time (Section 4.3 attributes the O(dt^2) gap between the
+ * gas energy change and the radiation energy change to the first-order
+ * solve, and names solving the absorption system twice as the cure).
+ * Reading: the gap is the work term, which the system takes at the velocity
+ * u of the step while the kinetic energy change equals the momentum change
+ * times the mean of v^n and v^n + d(rho v)/rho.  So the system is solved a
+ * first time at u (the Step 3 estimate, or v^n), giving the Step 4 momentum
+ * change d4; then again, from the same right-hand side r4 and T^n, at the
+ * time-centred velocity v^n + d4/(2 rho).  The second solution is the
+ * step's.  The scattering step keeps u. */
 static int source_cell(const or_problem *p, double dt, double rho, double sa,
                        double ss, const double *v, const double *vt,
                        const double *In, const double *dFc, double Tn,
@@ -502,7 +512,21 @@ static int source_cell(const or_problem *p, double dt, double rho, double sa,
   const int to5 = ss > sa;
   for (int m = 0; m < N; ++m) r4[m] = In[m] + (to5 ? 0.0 : dFc[m]);
   double T4;
-  const int it = or_absorption_cell(p, dt, sa, rho, vt, r4, Tn, I4, &T4);
+  /* the gas gains the momentum the radiation loses, at the true rate: C/chat
+   * times the radiation's change with a reduced speed of light */
+  const double gas = p->chat > 0.0 ? p->C / p->chat : 1.0;
+  int it = or_absorption_cell(p, dt, sa, rho, vt, r4, Tn, I4, &T4);
+  if (p->second_order && it > 0) {
+    double uc[3];
+    for (int k = 0; k < 3; ++k) {
+      double dH = 0.0; /* sum_m n_m W_m (I'_m - r4_m) */
+      for (int m = 0; m < N; ++m) dH += p->mu[3 * m + k] * p->w[m] * (I4[m] - r4[m]);
+      const double d4 = -gas * (FOURPI * p->P / p->C) * dH;
+      uc[k] = v[k] + d4 / (2.0 * rho);
+    }
+    const int it2 = or_absorption_cell(p, dt, sa, rho, uc, r4, Tn, I4, &T4);
+    it = it2 > 0 ? (it2 > it ? it2 : it) : it2;
+  }
   for (int m = 0; m < N; ++m) r5[m] = I4[m] + (to5 ? dFc[m] : 0.0);
   const int st = or_scattering_cell(p, dt, ss, vt, r5, Inew);
   double H4[3] = {0, 0, 0}, Hr4[3] = {0, 0, 0}, H5[3] = {0, 0, 0}, Hr5[3] = {0, 0, 0};
@@ -518,9 +542,6 @@ static int source_cell(const or_problem *p, double dt, double rho, double sa,
   const double cv = rho * p->R / (p->gamma - 1.0);
   const double dET = cv * (T4 - Tn);
   double m0sq = 0, m1sq = 0;
-  /* the gas gains the momentum the radiation loses, at the true rate: C/chat
-   * times the radiation's change with a reduced speed of light */
-  const double gas = p->chat > 0.0 ? p->C / p->chat : 1.0;
   for (int k = 0; k < 3; ++k) {
     const double d4 = -gas * (FOURPI * p->P / p->C) * (H4[k] - Hr4[k]);
     const double d5 = -gas * (FOURPI * p->P / p->C) * (H5[k] - Hr5[k]);

@@ -55,6 +55,11 @@ typedef struct or_problem {
                             energy and momentum at the true rate (the
                             reduced-speed-of-light approximation that
                             Section 6 combines with the method)             */
+  int second_order;      /* 1: the absorption system of Section 4.3 solved
+                            twice per step, the second time with the
+                            time-centred velocity of the first solution
+                            (the second-order-in-time variant that section
+                            names; see source_cell)                         */
 } or_problem;
 
 /* Angular quadrature of I (Section 3): E = 4pi sum W I, F_k = 4pi sum W mu_k I,
