@@ -48,7 +48,7 @@ def load_traffic(kernel: str, workload: str):
         return None
 
 
-def run_gpu(wl, precision: str, steps: int, warmup: int):
+def run_gpu(wl, precision: str, steps: int, warmup: int, second_order: bool = False):
     import torch
 
     import workloads as W
@@ -58,7 +58,7 @@ def run_gpu(wl, precision: str, steps: int, warmup: int):
     mu, w = quadrature_for(wl.quad)
     T = torch.as_tensor(wl.T).cuda()
     I0 = W.equilibrium_intensity(T, len(w), xp=torch)  # (nang, ncell), expanded view
-    s = Solver(wl, precision=precision, mu=mu, w=w, I0=I0)
+    s = Solver(wl, precision=precision, mu=mu, w=w, I0=I0, second_order=second_order)
     del I0
     info = rt.rt_get_info(s.ctx)
     stream = torch.cuda.current_stream().cuda_stream
@@ -185,6 +185,9 @@ def main():
                     help="run the CPU-baseline leg alone (no GPU) and print its JSON")
     ap.add_argument("--only", choices=["fp64", "mixed"], default=None,
                     help="profiling: run one precision only and print its timing")
+    ap.add_argument("--second-order", action="store_true",
+                    help="with --only: time the step with the absorption system solved twice "
+                         "(the thread-per-cell kernel)")
     ap.add_argument("--serve-requests", type=int, default=200,
                     help="requests of the serving trace (0: skip; 2000 = the full stream)")
     ap.add_argument("--serve-load", type=float, default=0.8)
@@ -195,6 +198,8 @@ def main():
                     help="profiling: time a plain device-to-device copy of this many GiB "
                          "(counter calibration) and exit")
     args = ap.parse_args()
+    if args.second_order and not args.only:
+        ap.error("--second-order goes with --only")
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}): the library "
               "has no multi-GPU path (the domain decomposition it would use is a design, "
@@ -240,10 +245,13 @@ def main():
     print(f"bench: {wname} fp64 warmup={args.warmup} steps={args.steps}", file=sys.stderr,
           flush=True)
     if args.only:
-        r = run_gpu(wl, args.only, args.steps, args.warmup)
-        print(json.dumps({"precision": args.only, "kernel_ms": r["kernel_ms"],
-                          "value": r["value"], "achieved_gbs": r["achieved_gbs"],
-                          "bytes_per_launch": r["bytes_per_launch"]}), flush=True)
+        r = run_gpu(wl, args.only, args.steps, args.warmup, second_order=args.second_order)
+        print(json.dumps({"precision": args.only, "second_order": args.second_order,
+                          "kernel_ms": r["kernel_ms"], "value": r["value"],
+                          "achieved_gbs": r["achieved_gbs"],
+                          "bytes_per_launch": r["bytes_per_launch"],
+                          "grid_blocks": r["grid_blocks"],
+                          "block_threads": r["block_threads"]}), flush=True)
         return
     r64 = run_gpu(wl, "fp64", args.steps, args.warmup)
     print(f"bench: fp64 {r64['value']:.4g} cell-angle/s, kernel {r64['kernel_ms']:.3f} ms",

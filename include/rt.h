@@ -76,6 +76,17 @@ enum { RT_QUAD_GAUSS_LEGENDRE = 0, RT_QUAD_LEVEL_SYMMETRIC = 1 };
  * swamping the physical diffusion in optically thick media; kept for that
  * comparison. */
 #define RT_ORIGINAL_TRANSPORT 4u
+/* Flag: second order in time for the absorption step.  Section 4.3 traces the
+ * O(dt^2) gap between the gas energy change (Delta E_T + Delta E_K) and the
+ * radiation energy change to the single solve of the absorption system and
+ * names solving it twice as the remedy.  Reading: the system is solved at
+ * the step's velocity u (the Step 3 estimate, or v), the Step 4 momentum
+ * change d4 of that solution gives the time-centred velocity
+ * v + d4/(2 rho), and the system is solved again at that velocity from the
+ * same right-hand side and T^n; the second solution is the step's.  The
+ * scattering step keeps u.  Runs on the thread-per-cell step kernel (about
+ * twice the source-step work); RT_EUNSUPPORTED with RT_GAS_FEEDBACK. */
+#define RT_SECOND_ORDER 8u
 /* Number of entries of the totals vector. */
 #define RT_NTOT 12
 
@@ -104,7 +115,7 @@ typedef struct rt_params {
   double r_ideal;      /* ideal gas constant > 0; c_v = rho r/(gamma - 1)   */
   int precision;       /* RT_FP64 or RT_FP32_MIXED                          */
   unsigned flags;      /* RT_ESTIMATE_V | RT_GAS_FEEDBACK |
-                          RT_ORIGINAL_TRANSPORT                             */
+                          RT_ORIGINAL_TRANSPORT | RT_SECOND_ORDER           */
   double newton_rtol;  /* relative tolerance of the temperature Newton
                           iteration (e.g. 1e-14); <= 0 selects 1e-14        */
   int newton_maxit;    /* iteration limit (e.g. 64); <= 0 selects 64        */

@@ -290,6 +290,7 @@ int ctx_init_host(const rt_grid *g, const rt_angles *an, const rt_params *p, rt_
   if (!(p->c_reduced >= 0.0) || p->c_reduced > p->c) return RT_EINVAL;
   if (p->c_reduced > 0.0 && p->c_reduced < p->c && (p->flags & RT_ESTIMATE_V))
     return RT_EUNSUPPORTED;
+  if ((p->flags & RT_SECOND_ORDER) && (p->flags & RT_GAS_FEEDBACK)) return RT_EUNSUPPORTED;
 
   c->g = *g;
   c->p = *p;
@@ -314,6 +315,11 @@ int ctx_init_host(const rt_grid *g, const rt_angles *an, const rt_params *p, rt_
     if (s > c->cfl_sum) c->cfl_sum = s;
   }
   c->shape = pick_shape(N, c->all_periodic);
+  if (p->flags & RT_SECOND_ORDER) {
+    // the second absorption solve runs on the thread-per-cell kernel
+    c->shape.waves = c->shape.groups = 0;
+    c->shape.second = true;
+  }
   c->nblocks = (nc + 63) / 64;  // enough partial-total rows for either kernel
   return RT_OK;
 }

@@ -203,8 +203,55 @@ __global__ __launch_bounds__(kBlock) void k_transport(StepArgs p) {
   }
 }
 
+// Temperature of the reduced absorption system (Section 4.3) from its
+// per-cell angle sums at velocity u (uu = u.u): the quartic
+// c_v (T - T^n) = h0 + h1 T^4/4pi by Newton from T^n.  Returns T and sets
+// X = T^4/4pi, Q = q0 + q1 X, the iteration count and convergence.
+struct AbsSums {
+  double Sr, Se, S1, Rr, Re, R1, Ar, Ae, A1;
+};
+__device__ __forceinline__ double abs_solve(const StepArgs &p, const AbsSums &a, double uu,
+                                            double sa, double cv, double Tn, double &X,
+                                            double &Q, int &it, bool &conv) {
+  const double C = p.C, P = p.P, dt = p.dt;
+  const double kap = dt * sa / C;
+  const double qden = 1.0 + kap * a.A1;
+  const double q0 = a.Ar / qden, q1 = a.Ae / qden;
+  const double j0 = a.Sr - kap * a.S1 * q0, j1 = a.Se - kap * a.S1 * q1;
+  const double k0 = a.Rr - kap * a.R1 * q0, k1 = a.Re - kap * a.R1 * q1;
+  const double beta = P * C * (1.0 - uu / (C * C)) * sa * dt;
+  const double g8 = 8.0 * kPi * P * sa * dt;
+  const double h0 = -g8 * (k0 - q0 / C) + kFourPi * beta * j0;
+  const double h1 = -g8 * (k1 - q1 / C) - kFourPi * beta * (1.0 - j1);
+  const double h1q = h1 * (1.0 / kFourPi);
+  double T = Tn;
+  conv = false;
+  for (it = 1; it <= p.maxit; ++it) {
+    const double T3 = T * T * T;
+    const double f = cv * (T - Tn) - h0 - h1q * T3 * T;
+    const double fp = cv - 4.0 * h1q * T3;
+    const double dT = f / fp;
+    T -= dT;
+    if (fabs(dT) <= p.rtol * fabs(T)) {
+      conv = true;
+      break;
+    }
+  }
+  X = T * T * T * T * (1.0 / kFourPi);
+  Q = q0 + q1 * X;
+  return T;
+}
+
 // Fused step (FUSED) or source-only step reading dF_in (!FUSED).
-template <typename S, typename A, bool PER, bool FUSED>
+// SO: second order in time for the absorption step (Section 4.3 names
+// solving the absorption system twice): the system is solved at the step's
+// velocity u, the Step 4 momentum change d4 of that solution gives the
+// time-centred velocity uc = v^n + d4/(2 rho), and the system is solved
+// again at uc from the same right-hand side and T^n.  The scattering step
+// keeps u.  Pass 1 then stages the right-hand side (r4, or dF when dF is
+// routed to Step 5) instead of p_m, and pass 1b forms the sums of the second
+// solve and of the scattering step.
+template <typename S, typename A, bool PER, bool FUSED, bool SO>
 __global__ __launch_bounds__(kBlock) void k_step(StepArgs p) {
   const int c = blockIdx.x * kBlock + threadIdx.x;
   const bool active = c < p.ncell;
@@ -250,9 +297,14 @@ __global__ __launch_bounds__(kBlock) void k_step(StepArgs p) {
     const A dssC = A(dt * ss / C);
 
     // pass 1 accumulators (double)
-    double Sr = 0, Se = 0, S1 = 0, Rr = 0, Re = 0, R1 = 0, Ar = 0, Ae = 0, A1 = 0;
+    AbsSums ab{0, 0, 0, 0, 0, 0, 0, 0, 0};
     double Bp = 0, Pp = 0, Bb = 0, Bc = 0, B1 = 0, Bcc = 0, Be = 0, Bd = 0, Ee = 0, Ed = 0;
     double M0 = 0, M1 = 0, M2 = 0;
+    // SO: the Step 4 momentum change of the first solution from
+    // I'_m - r4_m = (-dt sa (C - t) r4_m + e_m X - kappa Q)/D_m:
+    // sum W n (-dt sa (C - t) r4)/D, sum W n e/D, sum W n/D
+    const A AC = A(C);
+    double Hd[3] = {0, 0, 0}, He[3] = {0, 0, 0}, H1[3] = {0, 0, 0};
 
     for (int m = 0; m < p.nang; ++m) {
       const S *Im = Iin + (size_t)m * N;
@@ -268,69 +320,117 @@ __global__ __launch_bounds__(kBlock) void k_step(StepArgs p) {
       const A invD = A(1) / (D0 - dsa * t);
       const A e = E0 + A(3) * dsa * t;
       const A g = Auu + t * t;
-      const A invaw = A(1) / (AW0 - dss * t);
-      const A b = B0 + A(2) * dss * t - dssC * t * t;
-      const A cm = A(-3) * dss * t;
       const A r4 = to5 ? Ic : Ic + dF;
-      const A pm = r4 * invD + (to5 ? dF : A(0));
-      Iout[(size_t)m * N + c] = S(pm);
       const A WD = Wm * invD;
-      const A Wa = Wm * invaw;
-      const A Wad = Wa * invD;
-      Sr += double(WD * r4);
-      Se += double(WD * e);
-      S1 += double(WD);
-      Rr += double(WD * t * r4);
-      Re += double(WD * t * e);
-      R1 += double(WD * t);
-      Ar += double(WD * g * r4);
-      Ae += double(WD * g * e);
-      A1 += double(WD * g);
-      Bp += double(Wa * b * pm);
-      Pp += double(Wa * pm);
-      Bb += double(Wa * b);
-      Bc += double(Wa * b * cm);
-      B1 += double(Wa);
-      Bcc += double(Wa * cm);
-      Be += double(Wad * b * e);
-      Bd += double(Wad * b);
-      Ee += double(Wad * e);
-      Ed += double(Wad);
+      ab.Sr += double(WD * r4);
+      ab.Se += double(WD * e);
+      ab.S1 += double(WD);
+      ab.Rr += double(WD * t * r4);
+      ab.Re += double(WD * t * e);
+      ab.R1 += double(WD * t);
+      ab.Ar += double(WD * g * r4);
+      ab.Ae += double(WD * g * e);
+      ab.A1 += double(WD * g);
       const A WI = Wm * (Ic + dF);
       M0 += double(n0 * WI);
       M1 += double(n1 * WI);
       M2 += double(n2 * WI);
+      if constexpr (SO) {
+        Iout[(size_t)m * N + c] = S(to5 ? dF : r4);
+        const double d[3] = {p.mu[m], p.mu[p.nang + m], p.mu[2 * p.nang + m]};
+        const double wd = double(WD), wr = double(-(WD * dsa * (AC - t) * r4)),
+                     we = double(WD * e);
+        for (int k = 0; k < 3; ++k) {
+          Hd[k] += d[k] * wr;
+          He[k] += d[k] * we;
+          H1[k] += d[k] * wd;
+        }
+      } else {
+        const A invaw = A(1) / (AW0 - dss * t);
+        const A b = B0 + A(2) * dss * t - dssC * t * t;
+        const A cm = A(-3) * dss * t;
+        const A pm = r4 * invD + (to5 ? dF : A(0));
+        Iout[(size_t)m * N + c] = S(pm);
+        const A Wa = Wm * invaw;
+        const A Wad = Wa * invD;
+        Bp += double(Wa * b * pm);
+        Pp += double(Wa * pm);
+        Bb += double(Wa * b);
+        Bc += double(Wa * b * cm);
+        B1 += double(Wa);
+        Bcc += double(Wa * cm);
+        Be += double(Wad * b * e);
+        Bd += double(Wad * b);
+        Ee += double(Wad * e);
+        Ed += double(Wad);
+      }
     }
 
     // Step 4: scalar quartic in T' (FP64)
     const double kap = dt * sa / C;
-    const double qden = 1.0 + kap * A1;
-    const double q0 = Ar / qden, q1 = Ae / qden;
-    const double j0 = Sr - kap * S1 * q0, j1 = Se - kap * S1 * q1;
-    const double k0 = Rr - kap * R1 * q0, k1 = Re - kap * R1 * q1;
-    const double beta = P * C * (1.0 - uu / (C * C)) * sa * dt;
-    const double g8 = 8.0 * kPi * P * sa * dt;
-    const double h0 = -g8 * (k0 - q0 / C) + kFourPi * beta * j0;
-    const double h1 = -g8 * (k1 - q1 / C) - kFourPi * beta * (1.0 - j1);
     const double cv = rho * p.cvfac;
-    const double h1q = h1 * (1.0 / kFourPi);
-    double T = Tn;
-    int it = 0;
-    bool conv = false;
-    for (it = 1; it <= p.maxit; ++it) {
-      const double T3 = T * T * T;
-      const double f = cv * (T - Tn) - h0 - h1q * T3 * T;
-      const double fp = cv - 4.0 * h1q * T3;
-      const double dT = f / fp;
-      T -= dT;
-      if (fabs(dT) <= p.rtol * fabs(T)) {
-        conv = true;
-        break;
+    double X, Q;
+    int it;
+    bool conv;
+    double T = abs_solve(p, ab, uu, sa, cv, Tn, X, Q, it, conv);
+    // absorption at the time-centred velocity (SO), else at u
+    double ua0 = u0, ua1 = u1, ua2 = u2;
+    if constexpr (SO) {
+      // Step 4 momentum change of the first solution, as the gas sees it
+      const double fm = -p.gasfac * kFourPi * P / C;
+      ua0 = v0 + fm * (Hd[0] + X * He[0] - kap * Q * H1[0]) / (2.0 * rho);
+      ua1 = v1 + fm * (Hd[1] + X * He[1] - kap * Q * H1[1]) / (2.0 * rho);
+      ua2 = v2 + fm * (Hd[2] + X * He[2] - kap * Q * H1[2]) / (2.0 * rho);
+      const double uua = ua0 * ua0 + ua1 * ua1 + ua2 * ua2;
+      const A Ua0 = A(ua0), Ua1 = A(ua1), Ua2 = A(ua2), Auua = A(uua);
+      AbsSums a2{0, 0, 0, 0, 0, 0, 0, 0, 0};
+      // pass 1b: the sums of the second solve and of the scattering step
+      for (int m = 0; m < p.nang; ++m) {
+        const size_t at = (size_t)m * N + c;
+        const A n0 = A(p.mu[m]), n1 = A(p.mu[p.nang + m]), n2 = A(p.mu[2 * p.nang + m]);
+        const A Wm = A(p.w[m]);
+        const A q = A(Iout[at]);
+        const A r4 = to5 ? A(Iin[at]) : q;
+        const A ta = n0 * Ua0 + n1 * Ua1 + n2 * Ua2;
+        const A invD = A(1) / (D0 - dsa * ta);
+        const A e = E0 + A(3) * dsa * ta;
+        const A g = Auua + ta * ta;
+        const A WD = Wm * invD;
+        a2.Sr += double(WD * r4);
+        a2.Se += double(WD * e);
+        a2.S1 += double(WD);
+        a2.Rr += double(WD * ta * r4);
+        a2.Re += double(WD * ta * e);
+        a2.R1 += double(WD * ta);
+        a2.Ar += double(WD * g * r4);
+        a2.Ae += double(WD * g * e);
+        a2.A1 += double(WD * g);
+        const A t = n0 * Au0 + n1 * Au1 + n2 * Au2;
+        const A invaw = A(1) / (AW0 - dss * t);
+        const A b = B0 + A(2) * dss * t - dssC * t * t;
+        const A cm = A(-3) * dss * t;
+        const A pm = r4 * invD + (to5 ? q : A(0));
+        Iout[at] = S(pm);
+        const A Wa = Wm * invaw;
+        const A Wad = Wa * invD;
+        Bp += double(Wa * b * pm);
+        Pp += double(Wa * pm);
+        Bb += double(Wa * b);
+        Bc += double(Wa * b * cm);
+        B1 += double(Wa);
+        Bcc += double(Wa * cm);
+        Be += double(Wad * b * e);
+        Bd += double(Wad * b);
+        Ee += double(Wad * e);
+        Ed += double(Wad);
       }
+      int it2;
+      bool conv2;
+      T = abs_solve(p, a2, uua, sa, cv, Tn, X, Q, it2, conv2);
+      it = it2 > it ? it2 : it;
+      conv = conv && conv2;
     }
     if (!conv || !(T > 0.0) || !isfinite(T)) atomicOr(p.status, 1);
-    const double X = T * T * T * T * (1.0 / kFourPi);
-    const double Q = q0 + q1 * X;
 
     // Step 5: the 2 x 2 system of the scattering step
     const double Sbr = Bp + X * Be - kap * Q * Bd;
@@ -342,13 +442,15 @@ __global__ __launch_bounds__(kBlock) void k_step(StepArgs p) {
 
     // pass 2: new intensities and their moments
     const A AX = A(X), AkQ = A(kap * Q), As1 = A(s1), As2 = A(s2);
+    const A Ua0 = A(ua0), Ua1 = A(ua1), Ua2 = A(ua2);
     double mom[kNmom] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
     double imin = 1.0e300;
     for (int m = 0; m < p.nang; ++m) {
       const A n0 = A(p.mu[m]), n1 = A(p.mu[p.nang + m]), n2 = A(p.mu[2 * p.nang + m]);
       const A t = n0 * Au0 + n1 * Au1 + n2 * Au2;
-      const A invD = A(1) / (D0 - dsa * t);
-      const A e = E0 + A(3) * dsa * t;
+      const A ta = SO ? n0 * Ua0 + n1 * Ua1 + n2 * Ua2 : t;
+      const A invD = A(1) / (D0 - dsa * ta);
+      const A e = E0 + A(3) * dsa * ta;
       const A invaw = A(1) / (AW0 - dss * t);
       const A cm = A(-3) * dss * t;
       const size_t at = (size_t)m * N + c;

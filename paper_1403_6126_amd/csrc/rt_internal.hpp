@@ -22,6 +22,7 @@ constexpr int kMaxGroupsPerWave = 4;
 struct KShape {
   int waves = 0, groups = 0;
   bool periodic = true;
+  bool second = false;  // second-order absorption (thread-per-cell kernel only)
 };
 
 // One request of a packed persistent launch: a whole solve of nsteps steps

@@ -27,6 +27,7 @@ RT_QUAD_GAUSS_LEGENDRE, RT_QUAD_LEVEL_SYMMETRIC = 0, 1
 RT_ESTIMATE_V = 1
 RT_GAS_FEEDBACK = 2
 RT_ORIGINAL_TRANSPORT = 4
+RT_SECOND_ORDER = 8
 RT_NTOT = 12
 RT_MAX_ANGLES = 1024
 

@@ -31,7 +31,8 @@ class Solver:
     def __init__(self, wl, precision: str | None = None, mu=None, w=None,
                  estimate_v: bool = True, I0=None, T0=None, newton_rtol=1e-14,
                  newton_maxit=64, device="cuda", feedback: bool = False,
-                 original_transport: bool = False, c_reduced: float = 0.0):
+                 original_transport: bool = False, c_reduced: float = 0.0,
+                 second_order: bool = False):
         import torch
         self.torch = torch
         self.wl = wl
@@ -47,7 +48,8 @@ class Solver:
         self.ncell = nc
         grid = rt.make_grid(wl.ndim, wl.n, wl.dx, wl.bc)
         flags = (rt.RT_ESTIMATE_V if estimate_v else 0) | (rt.RT_GAS_FEEDBACK if feedback else 0) \
-            | (rt.RT_ORIGINAL_TRANSPORT if original_transport else 0)
+            | (rt.RT_ORIGINAL_TRANSPORT if original_transport else 0) \
+            | (rt.RT_SECOND_ORDER if second_order else 0)
         params = rt.make_params(wl.C, wl.P, wl.gamma, wl.R, self.precision, flags, newton_rtol,
                                 newton_maxit, c_reduced)
         self.ctx = rt.rt_create(grid, self.mu, self.w, params)

@@ -13,3 +13,11 @@ def test_bench_refuses_several_gpus():
     assert r.returncode == 2
     assert "one GPU" in r.stderr
     assert r.stdout == ""
+
+
+def test_bench_second_order_needs_only():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--second-order"],
+                       capture_output=True, text=True, timeout=120, cwd=ROOT)
+    assert r.returncode == 2
+    assert "--only" in r.stderr
+    assert r.stdout == ""

@@ -1,0 +1,135 @@
+"""GPU parity of the second-order-in-time absorption step (RT_SECOND_ORDER:
+the absorption system of Section 4.3 solved twice per step, the second time
+at the time-centred velocity) against the oracle's reading of it, and the
+energy property that motivates it."""
+import numpy as np
+import pytest
+
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+TOL64 = 1e-12
+
+
+def _nerr(a, b):
+    den = np.abs(b).max()
+    return float(np.abs(a - b).max() / den) if den > 0 else float(np.abs(a - b).max())
+
+
+def _solver(wl, **kw):
+    from paper_1403_6126_amd.solver import Solver
+    return Solver(wl, second_order=True, **kw)
+
+
+CASES = [
+    (3, (19, 13, 11), ("ls", 6), None, True),
+    (3, (9, 17, 5), ("ls", 8), None, False),
+    (2, (23, 21), ("ls", 8), ((W.BC_FIXED, W.BC_COPY), (W.BC_VACUUM, W.BC_FIXED), (0, 0)), True),
+    (1, (300,), ("gl", 8), None, True),
+    (1, (70,), ("gl", 330), ((W.BC_VACUUM, W.BC_FIXED), (0, 0), (0, 0)), False),
+]
+
+
+@pytest.mark.parametrize("ndim,shape,quad,bc,estimate_v", CASES)
+def test_small_cases_fp64(ndim, shape, quad, bc, estimate_v):
+    import oracle
+    wl = W.small_case(ndim, shape, quad, seed=31 + ndim, nsteps=4, kappa_a=3.0, kappa_s=2.0,
+                      vscale=0.05, bc=bc, ghost_seed=5 if bc else None, rho_s=0.5, T_s=0.2)
+    wl.sigma_s[::3] *= 5.0   # both routings of the transport increment
+    ref = oracle.run(wl, nsteps=4, estimate_v=estimate_v, second_order=True)
+    single = oracle.run(wl, nsteps=4, estimate_v=estimate_v)
+    s = _solver(wl, estimate_v=estimate_v)
+    print(f"case {wl.name} nang={s.nang} second order, estimate_v={estimate_v}", flush=True)
+    s.step(4)
+    st = s.state()
+    status = s.status()
+    s.close()
+    assert status == 0
+    refmap = dict(I=ref.I, T=ref.T, E=ref.E, F=ref.F, P=ref.Pr, dEgas=ref.dEgas, dMom=ref.dMom)
+    errs = {k: _nerr(st[k], v) for k, v in refmap.items()}
+    assert max(errs.values()) <= TOL64, errs
+    # the case tells the two schemes apart
+    assert _nerr(st["I"], single.I) > 1e-6
+
+
+def test_unfused_equals_fused():
+    wl = W.small_case(3, (16, 12, 10), ("ls", 6), seed=9, vscale=0.05, kappa_s=4.0)
+    wl.sigma_s[::2] *= 0.1
+    a = _solver(wl)
+    b = _solver(wl)
+    for _ in range(3):
+        a.step(1)
+        b.source(b.transport())
+    sa, sb = a.state(), b.state()
+    a.close()
+    b.close()
+    for k in ("I", "T", "E", "F", "P", "dEgas", "dMom"):
+        assert _nerr(sb[k], sa[k]) <= 1e-13, k
+
+
+def test_mixed_precision_within_1e5():
+    import oracle
+    wl = W.small_case(3, (18, 14, 11), ("ls", 8), seed=41, nsteps=20, kappa_a=1.0, kappa_s=3.0,
+                      vscale=0.02)
+    s = _solver(wl, precision="mixed")
+    s.step(wl.nsteps)
+    st = s.state()
+    assert s.status() == 0
+    s.close()
+    ref = oracle.run(wl, nsteps=wl.nsteps, second_order=True)
+    errs = {k: _nerr(st[k], v) for k, v in dict(E=ref.E, F=ref.F, T=ref.T).items()}
+    tref = ref.totals()
+    etot = lambda t: t[0] + t[1]
+    errs["energy"] = abs(etot(st["totals"]) - etot(tref)) / abs(etot(tref))
+    print("mixed errors", errs, flush=True)
+    assert max(errs.values()) <= 1e-5, errs
+
+
+def test_config2_full_size_sampled_step():
+    # 128^3, S8 in FP64: after one GPU step, one more GPU step is compared on
+    # sampled cells with one oracle step from the same state
+    import oracle
+    wl = W.config2()
+    s = _solver(wl)
+    print(f"case {wl.name} full size, second order: 1 step, then 1 compared step", flush=True)
+    s.step(1)
+    st0 = s.state()
+    s.step(1)
+    st1 = s.state()
+    assert s.status() == 0
+    s.close()
+    rng = np.random.default_rng(321)
+    cells = np.unique(np.concatenate([rng.choice(wl.ncell, 200, replace=False),
+                                      [0, wl.ncell - 1, 127, 128 * 128 - 1]]))
+    prob = oracle.Problem(wl, second_order=True)
+    ref = oracle.step_cells(prob, st0["I"], st0["T"], cells)
+    del st0
+    got = dict(I=st1["I"][:, cells], T=st1["T"][cells], E=st1["E"][cells], F=st1["F"][:, cells],
+               Pr=st1["P"][:, cells], dEgas=st1["dEgas"][cells], dMom=st1["dMom"][:, cells])
+    errs = {k: _nerr(got[k], ref[k]) for k in got}
+    print("sampled errors", errs, flush=True)
+    assert max(errs.values()) <= TOL64, errs
+
+
+def test_energy_error_falls_faster():
+    # uniform periodic box with pure absorption (no transport): the energy
+    # error of one step, sum dE_gas + P sum dE_r, falls as dt^2 with one
+    # absorption solve and faster than dt^2.6 with two
+    from paper_1403_6126_amd.solver import Solver
+    from test_oracle_second_order import uniform_box
+    wl = uniform_box()
+    errs = {}
+    for so in (False, True):
+        for dt in (2.5e-3, 1.25e-3):
+            s = Solver(wl, estimate_v=False, second_order=so)
+            E0 = s.moments().state()["E"]
+            s.step(1, dt=dt)
+            st = s.state()
+            s.close()
+            errs[so, dt] = float(np.sum(st["dEgas"]) + wl.P * np.sum(st["E"] - E0)) * wl.cell_volume
+    o1 = np.log2(abs(errs[False, 2.5e-3] / errs[False, 1.25e-3]))
+    o2 = np.log2(abs(errs[True, 2.5e-3] / errs[True, 1.25e-3]))
+    print("energy errors", errs, flush=True)
+    assert 1.7 < o1 < 2.3 and o2 > 2.6, (o1, o2)
+    assert abs(errs[True, 1.25e-3]) < 1e-2 * abs(errs[False, 1.25e-3])
