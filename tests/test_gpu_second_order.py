@@ -133,3 +133,29 @@ def test_energy_error_falls_faster():
     print("energy errors", errs, flush=True)
     assert 1.7 < o1 < 2.3 and o2 > 2.6, (o1, o2)
     assert abs(errs[True, 1.25e-3]) < 1e-2 * abs(errs[False, 1.25e-3])
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", TOL64), ("mixed", 1e-5)])
+def test_with_reduced_speed_of_light(precision, tol):
+    # the centred velocity takes the gas's momentum change, C/c_hat times the
+    # radiation's (the library scales it by the same factor it applies to its
+    # gas outputs)
+    import oracle
+    wl = W.small_case(3, (15, 11, 9), ("ls", 6), seed=77, nsteps=4, kappa_a=3.0, kappa_s=1.0,
+                      vscale=0.05, rho_s=0.5, T_s=0.2)
+    chat = wl.C / 3.0
+    ref = oracle.run(wl, nsteps=4, estimate_v=False, c_reduced=chat, second_order=True)
+    s = _solver(wl, precision=precision, estimate_v=False, c_reduced=chat)
+    print(f"case {wl.name} second order, c_reduced = C/3, {precision}", flush=True)
+    s.step(4)
+    st = s.state()
+    status = s.status()
+    s.close()
+    assert status == 0
+    if precision == "fp64":
+        refmap = dict(I=ref.I, T=ref.T, E=ref.E, F=ref.F, P=ref.Pr, dEgas=ref.dEgas,
+                      dMom=ref.dMom)
+    else:
+        refmap = dict(E=ref.E, F=ref.F, T=ref.T)
+    errs = {k: _nerr(st[k], v) for k, v in refmap.items()}
+    assert max(errs.values()) <= tol, errs

@@ -82,3 +82,25 @@ def test_scattering_energy_unchanged():
     _, a = energy_error(wl, 2e-3)
     _, b = energy_error(wl, 2e-3, second_order=True)
     assert np.array_equal(a.I, b.I) and np.array_equal(a.T, b.T)
+
+
+def test_energy_error_order_reduced_speed():
+    # with a reduced speed of light c_hat the gas sees C/c_hat times the
+    # radiation's momentum change, and the centred velocity takes the gas's
+    # change; the conserved energy is (C/c_hat) P E_r + e_gas
+    wl = uniform_box()
+    chat = wl.C / 4.0
+
+    def err(dt, **kw):
+        prob = oracle.Problem(wl, estimate_v=False, c_reduced=chat, **kw)
+        st = oracle.State(prob)
+        E0 = st.E.copy()
+        st.step(dt=dt)
+        return float(np.sum(st.dEgas) + wl.C / chat * wl.P * np.sum(st.E - E0)) * wl.cell_volume
+    dts = [1e-2, 5e-3]
+    e1 = [err(dt) for dt in dts]
+    e2 = [err(dt, second_order=True) for dt in dts]
+    o1, o2 = math.log2(abs(e1[0] / e1[1])), math.log2(abs(e2[0] / e2[1]))
+    assert 1.5 < o1 < 2.3, o1
+    assert o2 > 2.6, o2
+    assert abs(e2[1]) < 1e-2 * abs(e1[1]), (e1, e2)
