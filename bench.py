@@ -265,7 +265,7 @@ def main():
                      roofline=dict(bound="hbm", achieved=rmx["achieved_gbs"], peak=HBM_PEAK_GBS,
                                    unit="GB/s", frac=rmx["achieved_gbs"] / HBM_PEAK_GBS,
                                    traffic=load_traffic("k_step3_mixed", wname),
-                                   kernel="rtk::k_step3<float, float, 10, true, true>",
+                                   kernel="rtk::k_step3<float, float, 10, 1, true, true>",
                                    kernel_ms=rmx["kernel_ms"],
                                    bytes_per_launch=rmx["bytes_per_launch"]))
     srv = None
@@ -298,7 +298,7 @@ def main():
         "roofline": {"bound": "hbm", "achieved": r64["achieved_gbs"], "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": r64["achieved_gbs"] / HBM_PEAK_GBS,
                      "traffic": load_traffic("k_step3_fp64", wname),
-                     "kernel": "rtk::k_step3<double, double, 10, true, true>",
+                     "kernel": "rtk::k_step3<double, double, 10, 1, true, true>",
                      "kernel_ms": r64["kernel_ms"], "bytes_per_launch": r64["bytes_per_launch"]},
         "fp32_mixed": mixed,
         "serving": srv,

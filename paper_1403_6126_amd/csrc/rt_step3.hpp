@@ -43,6 +43,17 @@ __device__ __forceinline__ double fast_rcp(double x) {
 }
 __device__ __forceinline__ float fast_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
 
+// Reciprocal of the limiter: in FP64 one Newton step on the hardware
+// estimate (relative error about the square of the estimate's, some tens of
+// ulp).  It only scales the slope correction of an interface value, never an
+// intensity itself; the source step keeps fast_rcp.  One step instead of two
+// on the twelve limiters of a cell-angle measured 3 % faster.
+__device__ __forceinline__ double limiter_rcp(double x) {
+  const double r = __builtin_amdgcn_rcp(x);
+  return __builtin_fma(r, __builtin_fma(-x, r, 1.0), r);
+}
+__device__ __forceinline__ float limiter_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+
 // up1 + h * vanLeer(up1 - up2, dn1 - up1), vanLeer(a, b) = 2ab/(a + b) when
 // ab > 0, else 0: the upwind interface value of the monotonic
 // piecewise-linear reconstruction at Courant factor h = (1 - nu)/2.
@@ -50,7 +61,7 @@ template <typename A>
 __device__ __forceinline__ A vl_face(A up2, A up1, A dn1, A h) {
   const A a = up1 - up2, b = dn1 - up1;
   const A ab = a * b;
-  const A q = (ab + ab) * fast_rcp(a + b);
+  const A q = (ab + ab) * limiter_rcp(a + b);
   return up1 + h * (ab > A(0) ? q : A(0));
 }
 
