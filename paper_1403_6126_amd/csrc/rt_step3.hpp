@@ -54,15 +54,17 @@ __device__ __forceinline__ double limiter_rcp(double x) {
 }
 __device__ __forceinline__ float limiter_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
 
-// up1 + h * vanLeer(up1 - up2, dn1 - up1), vanLeer(a, b) = 2ab/(a + b) when
-// ab > 0, else 0: the upwind interface value of the monotonic
-// piecewise-linear reconstruction at Courant factor h = (1 - nu)/2.
+// up1 + (h2/2) * vanLeer(up1 - up2, dn1 - up1), vanLeer(a, b) = 2ab/(a + b)
+// when ab > 0, else 0: the upwind interface value of the monotonic
+// piecewise-linear reconstruction at Courant number nu, h2 = 1 - nu.  The
+// factor 2 of the limiter and the 1/2 of the Courant factor cancel exactly
+// (scaling by 2 is exact), which saves an instruction per face.
 template <typename A>
-__device__ __forceinline__ A vl_face(A up2, A up1, A dn1, A h) {
+__device__ __forceinline__ A vl_face(A up2, A up1, A dn1, A h2) {
   const A a = up1 - up2, b = dn1 - up1;
   const A ab = a * b;
-  const A q = (ab + ab) * limiter_rcp(a + b);
-  return up1 + h * (ab > A(0) ? q : A(0));
+  const A q = ab * limiter_rcp(a + b);
+  return up1 + h2 * (ab > A(0) ? q : A(0));
 }
 
 // Stencil of one cell along one axis.
@@ -71,7 +73,7 @@ struct Stencil {
   int idx[4];   // cells at offsets -2, -1, +1, +2 (wrapped, or the edge cell)
   int kind[4];  // 0 read the cell, 1 fixed table, 2 vacuum
   A wv[4][3];   // 3 v J at those cells
-  A aL, aR, hL, hR;
+  A aL, aR, hL, hR;  // hL, hR: 1 - nu of the IV faces (twice the table's)
   double uL, uR;
 };
 
@@ -102,17 +104,20 @@ __device__ __forceinline__ void load_stencil(const StepArgs &p, int c, const int
   }
   s.aL = A(p.faces[(size_t)(d * 3 + 0) * N + c]);
   s.hL = A(p.faces[(size_t)(d * 3 + 1) * N + c]);
+  s.hL += s.hL;
   s.uL = p.faces[(size_t)(d * 3 + 2) * N + c];
   if (PER || q[d] + 1 < n || p.bc[d][1] == kPeriodic) {
     const int cr = s.idx[2];
     s.aR = A(p.faces[(size_t)(d * 3 + 0) * N + cr]);
     s.hR = A(p.faces[(size_t)(d * 3 + 1) * N + cr]);
+    s.hR += s.hR;
     s.uR = p.faces[(size_t)(d * 3 + 2) * N + cr];
   } else {
     // high non-periodic boundary: the ghost copies this cell's fields
     const double u = p.v[(size_t)d * N + c];
     s.aR = A(alpha_of(p.sa[c] + p.ss[c], p.dl10[d]));
     s.hR = A(0.5 * (1.0 - fabs(u) * p.dt_dx[d]));
+    s.hR += s.hR;
     s.uR = u;
   }
 }
@@ -296,7 +301,7 @@ __device__ __forceinline__ void step3_tile(const StepArgs &p, int blk, int G, St
           const A Im1 = plane_value<S, A, PER>(p, r[0], s.idx[1], s.kind[1], 0, d, m, mud);
           const A Ip1 = plane_value<S, A, PER>(p, r[1], s.idx[2], s.kind[2], 1, d, m, mud);
           const A Itm1 = Im1 - IV[1] * invC, Itp1 = Ip1 - IV[2] * invC;
-          const A h = A(0.5) * (A(1) - AC * fabs(mud) * dtdx);
+          const A h = A(1) - AC * fabs(mud) * dtdx;  // 1 - nu
           A upR, upL;
           if (mud > A(0)) {
             const A Im2 = plane_value<S, A, PER>(p, r[2], s.idx[0], s.kind[0], 0, d, m, mud);
