@@ -74,6 +74,7 @@ struct Stencil {
   int kind[4];  // 0 read the cell, 1 fixed table, 2 vacuum
   A wv[4][3];   // 3 v J at those cells
   A aL, aR, hL, hR;  // hL, hR: 1 - nu of the IV faces (twice the table's)
+  A bL, bR;          // (1 - alpha)/2: the weight of the sum of the two centre values
   double uL, uR;
 };
 
@@ -120,6 +121,8 @@ __device__ __forceinline__ void load_stencil(const StepArgs &p, int c, const int
     s.hR += s.hR;
     s.uR = u;
   }
+  s.bL = A(0.5) * (A(1) - s.aL);
+  s.bR = A(0.5) * (A(1) - s.aR);
 }
 
 // Intensity at a stencil cell from the value raw read at its (clamped) cell
@@ -314,9 +317,9 @@ __device__ __forceinline__ void step3_tile(const StepArgs &p, int blk, int G, St
             upR = vl_face(Itp2, Itp1, Itc, h);
             upL = vl_face(Itp1, Itc, Itm1, h);
           }
-          const A cenR = A(0.5) * (Itc + Itp1), cenL = A(0.5) * (Itm1 + Itc);
-          const A phiR = AC * mud * (s.aR * upR + (A(1) - s.aR) * cenR);
-          const A phiL = AC * mud * (s.aL * upL + (A(1) - s.aL) * cenL);
+          // alpha I~*_up + (1 - alpha) I~_c of the two faces
+          const A xR = s.aR * upR + s.bR * (Itc + Itp1);
+          const A xL = s.aL * upL + s.bL * (Itm1 + Itc);
           A ivR, ivL;
           {
             const A u2 = posR ? IV[1] : IV[3], u1 = posR ? IVc : IV[2], d1 = posR ? IV[2] : IVc;
@@ -328,7 +331,8 @@ __device__ __forceinline__ void step3_tile(const StepArgs &p, int blk, int G, St
             const A f = vl_face(u2, u1, d1, s.hL);
             ivL = zeroL ? A(0.5) * (IV[1] + IVc) : f;
           }
-          dF[k] -= dtdx * ((phiR + mud * ivR) - (phiL + mud * ivL));
+          // the fluxes C mu x + mu IV* with mu dt/dx taken out of the difference
+          dF[k] -= (dtdx * mud) * ((AC * xR + ivR) - (AC * xL + ivL));
         }
       }
     }
