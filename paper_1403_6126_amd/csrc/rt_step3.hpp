@@ -31,29 +31,6 @@ namespace rtk {
 constexpr int kNsum = 22;        // per-cell sums of phase B
 constexpr int kChunk = 11;       // values reduced per LDS round
 
-// Reciprocal from the hardware estimate refined by Newton steps (two in
-// FP64; the FP32 estimate is used as is).  Within an ulp of a divide.
-__device__ __forceinline__ double fast_rcp(double x) {
-  double r = __builtin_amdgcn_rcp(x);
-  double e = __builtin_fma(-x, r, 1.0);
-  r = __builtin_fma(r, e, r);
-  e = __builtin_fma(-x, r, 1.0);
-  r = __builtin_fma(r, e, r);
-  return r;
-}
-__device__ __forceinline__ float fast_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
-
-// Reciprocal of the limiter: in FP64 one Newton step on the hardware
-// estimate (relative error about the square of the estimate's, some tens of
-// ulp).  It only scales the slope correction of an interface value, never an
-// intensity itself; the source step keeps fast_rcp.  One step instead of two
-// on the twelve limiters of a cell-angle measured 3 % faster.
-__device__ __forceinline__ double limiter_rcp(double x) {
-  const double r = __builtin_amdgcn_rcp(x);
-  return __builtin_fma(r, __builtin_fma(-x, r, 1.0), r);
-}
-__device__ __forceinline__ float limiter_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
-
 // up1 + (h2/2) * vanLeer(up1 - up2, dn1 - up1), vanLeer(a, b) = 2ab/(a + b)
 // when ab > 0, else 0: the upwind interface value of the monotonic
 // piecewise-linear reconstruction at Courant number nu, h2 = 1 - nu.  The
