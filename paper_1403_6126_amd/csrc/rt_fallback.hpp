@@ -287,7 +287,8 @@ __global__ __launch_bounds__(kBlock) void k_step(StepArgs p) {
     const double uu = u0 * u0 + u1 * u1 + u2 * u2;
     const bool to5 = ss > sa;  // Step 2 routing of dF
 
-    // per-angle coefficient pieces (arith type)
+    // per-angle coefficient pieces (arith type); their reciprocals come from
+    // fast_rcp, within an ulp of a divide
     const A Au0 = A(u0), Au1 = A(u1), Au2 = A(u2), Auu = A(uu);
     const A dsa = A(dt * sa), dss = A(dt * ss);
     const A D0 = A(1.0 + dt * sa * C);          // D_m = D0 - dsa t
@@ -317,7 +318,7 @@ __global__ __launch_bounds__(kBlock) void k_step(StepArgs p) {
       else
         dF = dFin ? A(dFin[(size_t)m * N + c]) : A(0);
       const A t = n0 * Au0 + n1 * Au1 + n2 * Au2;
-      const A invD = A(1) / (D0 - dsa * t);
+      const A invD = fast_rcp(D0 - dsa * t);
       const A e = E0 + A(3) * dsa * t;
       const A g = Auu + t * t;
       const A r4 = to5 ? Ic : Ic + dF;
@@ -346,7 +347,7 @@ __global__ __launch_bounds__(kBlock) void k_step(StepArgs p) {
           H1[k] += d[k] * wd;
         }
       } else {
-        const A invaw = A(1) / (AW0 - dss * t);
+        const A invaw = fast_rcp(AW0 - dss * t);
         const A b = B0 + A(2) * dss * t - dssC * t * t;
         const A cm = A(-3) * dss * t;
         const A pm = r4 * invD + (to5 ? dF : A(0));
@@ -392,7 +393,7 @@ __global__ __launch_bounds__(kBlock) void k_step(StepArgs p) {
         const A q = A(Iout[at]);
         const A r4 = to5 ? A(Iin[at]) : q;
         const A ta = n0 * Ua0 + n1 * Ua1 + n2 * Ua2;
-        const A invD = A(1) / (D0 - dsa * ta);
+        const A invD = fast_rcp(D0 - dsa * ta);
         const A e = E0 + A(3) * dsa * ta;
         const A g = Auua + ta * ta;
         const A WD = Wm * invD;
@@ -406,7 +407,7 @@ __global__ __launch_bounds__(kBlock) void k_step(StepArgs p) {
         a2.Ae += double(WD * g * e);
         a2.A1 += double(WD * g);
         const A t = n0 * Au0 + n1 * Au1 + n2 * Au2;
-        const A invaw = A(1) / (AW0 - dss * t);
+        const A invaw = fast_rcp(AW0 - dss * t);
         const A b = B0 + A(2) * dss * t - dssC * t * t;
         const A cm = A(-3) * dss * t;
         const A pm = r4 * invD + (to5 ? q : A(0));
@@ -449,9 +450,9 @@ __global__ __launch_bounds__(kBlock) void k_step(StepArgs p) {
       const A n0 = A(p.mu[m]), n1 = A(p.mu[p.nang + m]), n2 = A(p.mu[2 * p.nang + m]);
       const A t = n0 * Au0 + n1 * Au1 + n2 * Au2;
       const A ta = SO ? n0 * Ua0 + n1 * Ua1 + n2 * Ua2 : t;
-      const A invD = A(1) / (D0 - dsa * ta);
+      const A invD = fast_rcp(D0 - dsa * ta);
       const A e = E0 + A(3) * dsa * ta;
-      const A invaw = A(1) / (AW0 - dss * t);
+      const A invaw = fast_rcp(AW0 - dss * t);
       const A cm = A(-3) * dss * t;
       const size_t at = (size_t)m * N + c;
       const A pm = A(Iout[at]);
