@@ -169,7 +169,11 @@ typedef struct rt_out { /* device arrays; any pointer may be NULL */
  * directions.  Returns the number of directions, or a negative rt_status. */
 int rt_quadrature(int kind, int order, double *mu, double *w, int cap);
 
-/* Creates a context on the current HIP device: validates the grid, the angle
+/* Creates a context on the current HIP device for the problem Section 2 states
+ * (the transfer equation on a Cartesian grid of discrete ordinates, with the
+ * gas given by density, temperature, velocity and the two opacities) and
+ * Section 3 discretises (directions n_m with weights W_m): validates the
+ * grid, the angle
  * set (sum w = 1 within 1e-12; |n| = 1 within 1e-12 on 2D/3D grids, |n| <= 1
  * on 1D slabs, whose directions may be azimuthal averages (mu, 0, 0)) and the
  * parameters, copies the angle table to the device and allocates the
@@ -188,8 +192,14 @@ int rt_bind_intensity(rt_ctx *ctx, void *I_a, void *I_b);
 int rt_current_intensity(rt_ctx *ctx, void **I_cur);
 
 /* Ghost intensities for an RT_BC_FIXED face: host array [nang] (beams,
- * inflow).  Ghost zones are two cells deep and both layers take the table;
- * the ghost values of J, v and the opacities copy the edge cell. */
+ * inflow).  Section 4.1 Step 2 transports I through ghost zones; the
+ * paper's tests fix them to injected beams and background inflow (Sections
+ * 5.4 and 5.8).  Ghost zones are two cells deep and both layers take the
+ * table; the ghost values of J, v and the opacities copy the edge cell.
+ * Synchronises the device before the upload, so steps already queued on any
+ * stream read the previous table and later steps the new one.  RT_EINVAL
+ * for a bad axis or side or a face that is not RT_BC_FIXED; RT_EDEVICE
+ * when the copy fails. */
 int rt_set_fixed_bc(rt_ctx *ctx, int axis, int side, const double *I_ghost);
 
 /* Position-dependent ghost intensities for an RT_BC_FIXED face, for beams
@@ -222,8 +232,12 @@ int rt_transport(rt_ctx *ctx, double dt, const rt_fields *f, void *dF, void *str
 int rt_source_implicit(rt_ctx *ctx, double dt, const rt_fields *f, const void *dF,
                        rt_out *out, void *stream);
 
-/* nsteps fused steps (transport, velocity estimate, absorption, scattering,
- * quadrature; I read and written once per step).  out->dEgas and
+/* nsteps fused steps of the operator-split update of Section 4.1 (Steps 2-5
+ * and the gas source terms of Step 7): transport (Section 4.2), velocity
+ * estimate (Section 4.5), absorption (Section 4.3), scattering (Section 4.4)
+ * and quadrature (Section 3); I read and written once per step.  RT_ECFL
+ * when dt breaks the transport limit; RT_ESTATE without bound
+ * intensities.  out->dEgas and
  * out->dMom receive the sums over the nsteps steps; the moments and totals
  * are those after the last step. */
 int rt_step(rt_ctx *ctx, double dt, int nsteps, const rt_fields *f, rt_out *out,

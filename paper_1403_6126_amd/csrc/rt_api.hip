@@ -9,7 +9,7 @@
 #include <vector>
 
 #include "rt.h"
-#include "rt_fallback.hpp"
+#include "rt_cellwise.hpp"
 #include "rt_internal.hpp"
 
 namespace rtk {
@@ -529,11 +529,14 @@ int rt_set_fixed_bc(rt_ctx *c, int axis, int side, const double *tab) {
   const int f = axis * 2 + side;
   const size_t off = (size_t)f * c->nang;
   std::memcpy(&c->h_ghost[off], tab, sizeof(double) * c->nang);
+  // steps queued on a caller's stream may still read the table: the upload
+  // waits for them (the null-stream copy alone does not order against
+  // non-blocking streams)
+  if (!hip_ok(hipDeviceSynchronize())) return RT_EDEVICE;
   if (!hip_ok(hipMemcpy(c->d_ghost + off, tab, sizeof(double) * c->nang, hipMemcpyHostToDevice)))
     return RT_EDEVICE;
   // the angle table replaces a position-dependent one
   if (c->d_gface[f]) {
-    hipDeviceSynchronize();
     hipFree(c->d_gface[f]);
     c->d_gface[f] = nullptr;
   }

@@ -2,9 +2,9 @@
 
 * Shadow (Section 5.8 geometry: a collimated beam from the -x face, an
   absorbing ellipsoidal clump of density contrast 1e3, fixed background
-  inflow elsewhere): FP32-mixed against the FP64 oracle on a 32^3 copy, and
-  at the full 256^3 against the GPU FP64 path, block-averaged to 64^3.  The
-  64^3 copy against the oracle runs when RT_LONG=1 (minutes of CPU).
+  inflow elsewhere): FP32-mixed against the FP64 oracle on 32^3 and 64^3
+  copies (50 steps), and at the full 256^3 against the GPU FP64 path,
+  block-averaged to 64^3.
 * Advective diffusion (Section 5.5 in 3D, flow held at v, no velocity
   estimate): at 512x512x256 cells the variance of the pulse grows by 2 D t
   per axis, D = C/(3 sigma_s), and its centroid moves by v t; a 64x64x32
@@ -12,7 +12,6 @@
 Errors are normwise, max|a - b| / max|b| per field.
 """
 import math
-import os
 
 import numpy as np
 import pytest
@@ -85,8 +84,10 @@ def test_shadow_32_mixed_matches_oracle():
     assert max(errs["E"], errs["F"], errs["T"]) <= TOL_MIXED and drift <= TOL_MIXED, errs
 
 
-@pytest.mark.skipif(os.environ.get("RT_LONG") != "1", reason="minutes of CPU oracle; RT_LONG=1")
+@pytest.mark.timeout(900)
 def test_shadow_64_mixed_matches_oracle():
+    # the stated check of the shadow workload: the oracle on all host threads
+    # (about a minute on 16 cores)
     errs, drift = _shadow_vs_oracle(64, 50)
     assert max(errs["E"], errs["F"], errs["T"]) <= TOL_MIXED and drift <= TOL_MIXED, errs
 

@@ -77,3 +77,39 @@ def test_zero_steps_is_a_no_op():
     st = s.state()
     s.close()
     assert np.array_equal(st["I"], I0) and np.array_equal(st["T"], T0)
+
+
+def test_fixed_table_upload_is_ordered_after_queued_steps():
+    # rt_set_fixed_bc called while steps are still queued on a non-blocking
+    # stream: those steps read the old inflow table, the later ones the new
+    # table.  The oracle takes the same sequence.
+    import torch
+
+    import oracle
+    from paper_1403_6126_amd import rt
+    from paper_1403_6126_amd.solver import Solver
+    bc = ((W.BC_FIXED, W.BC_FIXED), (W.BC_PERIODIC, W.BC_PERIODIC), (W.BC_COPY, W.BC_VACUUM))
+    wl = W.small_case(3, (40, 24, 20), ("ls", 4), seed=78, vscale=0.02, bc=bc, ghost_seed=9)
+    n1, n2 = 40, 5
+    mu = oracle.Problem(wl).mu
+    tabs = wl.ghost(mu)
+    new_tab = 3.0 * tabs[(0, 0)] + 0.5
+    a = oracle.run(wl, nsteps=n1)
+    tabs_b = dict(tabs)
+    tabs_b[(0, 0)] = new_tab
+    b = oracle.State(oracle.Problem(wl, ghost=tabs_b), I0=a.I, T0=a.T).step(nsteps=n2)
+    stream = torch.cuda.Stream()
+    s = Solver(wl)
+    torch.cuda.synchronize()                         # the uploads of the set-up
+    with torch.cuda.stream(stream):
+        s.step(n1)                                   # queued, not waited for
+        rt.rt_set_fixed_bc(s.ctx, 0, 0, new_tab)     # host call while they run
+        s.step(n2)
+    stream.synchronize()
+    st = s.state()
+    status = s.status()
+    s.close()
+    assert status == 0
+    errs = {k: _nerr(st[k], r) for k, r in (("I", b.I), ("T", b.T), ("E", b.E))}
+    print("   errors", errs, flush=True)
+    assert max(errs.values()) <= TOL["fp64"], errs

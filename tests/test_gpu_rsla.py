@@ -50,9 +50,7 @@ def test_reduced_speed_matches_oracle(name, precision):
                                            ("dMom", ref.dMom))}
     print("   errors", errs, flush=True)
     tol = TOL[precision]
-    assert max(errs[k] for k in ("I", "T", "E", "F", "dEgas")) <= tol, errs
-    # the momentum exchange is a difference of nearly equal sums of I
-    assert errs["dMom"] <= (1e-10 if precision == "fp64" else 1e-3), errs
+    assert max(errs.values()) <= tol, errs
 
 
 def test_reduced_speed_longer_step_at_fixed_temperature():

@@ -74,3 +74,35 @@ def test_canonical_order_octants():
         blk = mu[o * per:(o + 1) * per]
         sg = [-1 if o & 1 else 1, -1 if o & 2 else 1, -1 if o & 4 else 1]
         assert np.all(np.sign(blk) == sg)
+
+
+def _dfact(k):
+    """(k)!! for odd k >= -1 ((-1)!! = 1)."""
+    out = 1
+    while k > 1:
+        out *= k
+        k -= 2
+    return out
+
+
+@pytest.mark.parametrize("order", [4, 6, 8, 10, 12, 14, 16])
+def test_level_symmetric_even_moments_exact(order):
+    # Section 3 asks the angle set to reproduce the angular moments of an
+    # isotropic field.  The sphere average of x^2a y^2b z^2c is
+    # (2a-1)!!(2b-1)!!(2c-1)!!/(2a+2b+2c+1)!!; a level-symmetric set of order
+    # N integrates every such monomial of degree up to N-2 exactly, so a
+    # wrong class weight at any order fails one of these.
+    mu, w = level_symmetric(order)
+    assert (w > 0).all()
+    worst = 0.0
+    for deg in range(0, order - 1, 2):
+        for a in range(0, deg // 2 + 1):
+            for b in range(0, deg // 2 - a + 1):
+                c = deg // 2 - a - b
+                got = w @ (mu[:, 0] ** (2 * a) * mu[:, 1] ** (2 * b) * mu[:, 2] ** (2 * c))
+                exact = (_dfact(2 * a - 1) * _dfact(2 * b - 1) * _dfact(2 * c - 1)
+                         / _dfact(2 * (a + b + c) + 1))
+                worst = max(worst, abs(got - exact))
+    assert worst <= 1e-14, worst
+    # the odd moments vanish by the octant symmetry
+    assert abs(w @ (mu[:, 0] ** 3 * mu[:, 1])) <= 1e-15
