@@ -14,13 +14,49 @@
 
 namespace rtk {
 
-// Interface table and IV basis (once per call).  faces[(d*3 + j)*ncell + c]
-// for the face between the cell below c along axis d (wrapped; the edge cell
-// itself at a non-periodic low boundary, whose ghost copies it) and c:
-// j = 0 alpha, 1 hv = (1 - |u| dt/dx)/2, 2 u.  wv = 3 v E/(4pi) of the
-// current moments into mom[10..12].
-__global__ __launch_bounds__(kBlock) void k_faces(StepArgs p, double *faces, double *mom) {
+// Interface table, per-call angle factors and IV basis (once per call).
+// faces[(d*3 + j)*ncell + c] for the face between the cell below c along
+// axis d (wrapped; the edge cell itself at a non-periodic low boundary,
+// whose ghost copies it) and c, with the face opacity and flow speed u the
+// means of the two cells (Section 4.2):
+//   j = 0  C alpha, the transport speed factor times C;
+//   j = 1  the lower cell's share of the centred IV value: 1 when the flow
+//          goes up the axis (u > 0, upwind = lower cell), 0 when it goes
+//          down, 1/2 at u = 0 (centred);
+//   j = 2  the signed van Leer factor of the IV value, sign(u) (1 - nu_v),
+//          nu_v = |u| dt/dx (0 at u = 0).
+// arec[m*kRec + f] (FP64, and FP32 copies) are the per-angle records of the
+// call: direction, 1 - C |mu_d| dt/dx_d, w, w n_d and w n_i n_j; records
+// nang .. nrec-1 (the padding slots of the wave-group kernel) are zero.
+// wv = 3 v E/(4pi) of the current moments into mom[10..12].  One thread per
+// cell and per record (max of the two).
+__global__ __launch_bounds__(kBlock) void k_faces(StepArgs p, double *faces, double *mom,
+                                                  double *arec, float *arecf, int nrec) {
   const int c = blockIdx.x * kBlock + threadIdx.x;
+  if (c < nrec) {
+    double r[kRec];
+    for (int f = 0; f < kRec; ++f) r[f] = 0.0;
+    if (c < p.nang) {
+      const double n[3] = {p.mu[c], p.mu[p.nang + c], p.mu[2 * p.nang + c]};
+      const double w = p.w[c];
+      for (int d = 0; d < 3; ++d) {
+        r[rec_n0 + d] = n[d];
+        r[rec_h0 + d] = 1.0 - p.C * fabs(n[d]) * p.dt_dx[d];
+        r[rec_wn0 + d] = w * n[d];
+      }
+      r[rec_w] = w;
+      r[rec_wnn + 0] = w * n[0] * n[0];
+      r[rec_wnn + 1] = w * n[1] * n[1];
+      r[rec_wnn + 2] = w * n[2] * n[2];
+      r[rec_wnn + 3] = w * n[0] * n[1];
+      r[rec_wnn + 4] = w * n[0] * n[2];
+      r[rec_wnn + 5] = w * n[1] * n[2];
+    }
+    for (int f = 0; f < kRec; ++f) {
+      arec[(size_t)c * kRec + f] = r[f];
+      arecf[(size_t)c * kRec + f] = float(r[f]);
+    }
+  }
   if (c >= p.ncell) return;
   const size_t N = (size_t)p.ncell;
   const double sig_c = p.sa[c] + p.ss[c];
@@ -35,9 +71,9 @@ __global__ __launch_bounds__(kBlock) void k_faces(StepArgs p, double *faces, dou
       cl = c;
     const double sig = 0.5 * ((p.sa[cl] + p.ss[cl]) + sig_c);
     const double u = 0.5 * (p.v[(size_t)d * N + cl] + p.v[(size_t)d * N + c]);
-    faces[(size_t)(d * 3 + 0) * N + c] = alpha_of(sig, p.dl10[d]);
-    faces[(size_t)(d * 3 + 1) * N + c] = 0.5 * (1.0 - fabs(u) * p.dt_dx[d]);
-    faces[(size_t)(d * 3 + 2) * N + c] = u;
+    faces[(size_t)(d * 3 + 0) * N + c] = p.C * alpha_of(sig, p.dl10[d]);
+    faces[(size_t)(d * 3 + 1) * N + c] = iv_lower_share(u);
+    faces[(size_t)(d * 3 + 2) * N + c] = iv_signed_factor(u, p.dt_dx[d]);
   }
   const double J = mom[c] * (1.0 / kFourPi);
   for (int k = 0; k < 3; ++k) mom[(size_t)(10 + k) * N + c] = p.ivfac * p.v[(size_t)k * N + c] * J;
@@ -72,12 +108,28 @@ void clear_stale_error() { (void)hipGetLastError(); }
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
-KShape pick_shape(int nang, bool periodic) {
+// Waves per block of the wave-group kernel by storage type: the angle
+// groups are dealt to at most this many waves (more groups per wave amortise
+// the per-cell work of a wave over more angles), and to up to kMaxWaves when
+// the groups would not fit kMaxGroupsPerWave per wave.
+#ifndef RT_GROUP_WAVES_F64
+#define RT_GROUP_WAVES_F64 4
+#endif
+#ifndef RT_GROUP_WAVES_F32
+#define RT_GROUP_WAVES_F32 8
+#endif
+
+KShape pick_shape(int nang, bool periodic, int precision) {
   KShape k;
   k.periodic = periodic;
   const int ng = (nang + kAnglesPerWave - 1) / kAnglesPerWave;
-  const int G = ng < kMaxWaves ? ng : kMaxWaves;
-  const int NG = (ng + G - 1) / G;
+  const int pref = precision == RT_FP32_MIXED ? RT_GROUP_WAVES_F32 : RT_GROUP_WAVES_F64;
+  int G = ng < pref ? ng : pref;
+  int NG = (ng + G - 1) / G;
+  if (NG > kMaxGroupsPerWave) {
+    G = ng < kMaxWaves ? ng : kMaxWaves;
+    NG = (ng + G - 1) / G;
+  }
   if (NG <= kMaxGroupsPerWave) {
     k.waves = G;
     k.groups = NG;
@@ -242,6 +294,8 @@ void ctx_fill_args(const rt_ctx *c, double dt_call, const rt_fields *f, StepArgs
   a.muf = c->d_muf;
   a.wf = c->d_wf;
   a.ghost = c->d_ghost;
+  a.arec = c->d_arec;
+  a.arecf = c->d_arecf;
   for (int f = 0; f < 6; ++f) a.gface[f] = c->d_gface[f];
   a.faces = c->faces;
   if (f) {
@@ -314,20 +368,24 @@ int ctx_init_host(const rt_grid *g, const rt_angles *an, const rt_params *p, rt_
     }
     if (s > c->cfl_sum) c->cfl_sum = s;
   }
-  c->shape = pick_shape(N, c->all_periodic);
+  c->shape = pick_shape(N, c->all_periodic, p->precision);
   if (p->flags & RT_SECOND_ORDER) {
     // the second absorption solve runs on the thread-per-cell kernel
     c->shape.waves = c->shape.groups = 0;
     c->shape.second = true;
   }
   c->nblocks = (nc + 63) / 64;  // enough partial-total rows for either kernel
+  // angle records: every slot of the wave-group kernel has one
+  // (the packed serving kernel runs the same groups on kMaxWaves waves)
+  const int slots = c->shape.waves ? kMaxWaves * c->shape.groups * kAnglesPerWave : 0;
+  c->nrec = slots > N ? slots : N;
   return RT_OK;
 }
 
 namespace {
 // Scratch layout: offsets of the pieces in one block.
 struct Plan {
-  size_t mu, w, muf, wf, ghost, mom0, mom1, faces, partials, status, total;
+  size_t mu, w, muf, wf, ghost, arec, arecf, mom0, mom1, faces, partials, status, total;
 };
 Plan plan_of(const rt_ctx *c) {
   Plan q;
@@ -343,6 +401,8 @@ Plan plan_of(const rt_ctx *c) {
   q.muf = take(sizeof(float) * 3 * N);
   q.wf = take(sizeof(float) * N);
   q.ghost = take(sizeof(double) * 6 * N);
+  q.arec = take(sizeof(double) * kRec * (size_t)c->nrec);
+  q.arecf = take(sizeof(float) * kRec * (size_t)c->nrec);
   q.mom0 = take(sizeof(double) * kNmomX * nc);
   q.mom1 = take(sizeof(double) * kNmomX * nc);
   q.faces = take(sizeof(double) * 9 * nc);
@@ -365,6 +425,8 @@ int ctx_attach_scratch(rt_ctx *c, char *base, hipStream_t s) {
   c->h_muf.assign(c->h_mu.begin(), c->h_mu.end());
   c->h_wf.assign(c->h_w.begin(), c->h_w.end());
   c->d_ghost = reinterpret_cast<double *>(base + q.ghost);
+  c->d_arec = reinterpret_cast<double *>(base + q.arec);
+  c->d_arecf = reinterpret_cast<float *>(base + q.arecf);
   c->mom[0] = reinterpret_cast<double *>(base + q.mom0);
   c->mom[1] = reinterpret_cast<double *>(base + q.mom1);
   c->faces = reinterpret_cast<double *>(base + q.faces);
@@ -381,6 +443,7 @@ int ctx_attach_scratch(rt_ctx *c, char *base, hipStream_t s) {
                             s)) &&
       hip_ok(hipMemcpyAsync(c->d_ghost, c->h_ghost.data(), sizeof(double) * 6 * N,
                             hipMemcpyHostToDevice, s)) &&
+
       hip_ok(hipMemsetAsync(c->status, 0, sizeof(int), s));
   return ok ? RT_OK : RT_EDEVICE;
 }
@@ -402,8 +465,9 @@ int ctx_prepare_call(rt_ctx *c, double dt, const rt_fields *f, hipStream_t s) {
   StepArgs a;
   ctx_fill_args(c, dt, f, a);
   clear_stale_error();
-  hipLaunchKernelGGL(k_faces, dim3((unsigned)cell_blocks(c)), dim3(kBlock), 0, s, a, c->faces,
-                     c->mom[c->mom_cur]);
+  const long long nthreads = c->ncell > c->nrec ? c->ncell : c->nrec;
+  hipLaunchKernelGGL(k_faces, dim3((unsigned)((nthreads + kBlock - 1) / kBlock)), dim3(kBlock), 0,
+                     s, a, c->faces, c->mom[c->mom_cur], c->d_arec, c->d_arecf, c->nrec);
   return hip_ok(hipGetLastError()) ? RT_OK : RT_EDEVICE;
 }
 

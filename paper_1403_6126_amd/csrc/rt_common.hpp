@@ -17,6 +17,16 @@ enum BcKind : int { kPeriodic = 0, kFixed = 1, kCopy = 2, kVacuum = 3 };
 constexpr int kNmomX = 13;  // moments (10) + 3 v J (3)
 constexpr int kMaxWaves = 8;  // waves per block of the wave-group kernel
 
+// Entries of a per-angle record (StepArgs::arec).
+enum RecField : int {
+  rec_n0 = 0, rec_n1, rec_n2,   // direction cosines
+  rec_h0, rec_h1, rec_h2,       // 1 - C |mu_d| dt/dx_d, d = 0..2
+  rec_w,                        // weight
+  rec_wn0, rec_wn1, rec_wn2,    // w n_d
+  rec_wnn,                      // 6 values: w n_x n_x, w n_y n_y, w n_z n_z, w n_x n_y, w n_x n_z, w n_y n_z
+  kRec = 16
+};
+
 // Arguments of every step kernel (passed by value).
 struct StepArgs {
   int ndim, n[3], ncell, nang;
@@ -33,6 +43,12 @@ struct StepArgs {
   const double *w;       // [nang]
   const float *muf;      // FP32 copies of mu and w (FP32 arithmetic)
   const float *wf;
+  // per call, one record of kRec values per angle (padded with zero records
+  // to the slots of the wave-group kernel): the direction, the Courant
+  // factors 1 - C |mu_d| dt/dx_d of the slope terms, and the quadrature
+  // weights of the moments (layout in rec_*)
+  const double *arec;
+  const float *arecf;
   const double *ghost;   // [3][2][nang] fixed-face ghost intensities
   const double *gface[6];  // per face (axis*2 + side): [nang][ncell / n[axis]]
                            // position-dependent ghosts of a fixed face, or null
@@ -40,7 +56,8 @@ struct StepArgs {
   double *v;             // [3][ncell]; written only with feedback
   int feedback;          // gas feedback: v <- v + d(rho v)/rho after the step
   double *T;
-  const double *faces;   // [3][3][ncell] alpha, hv, u of the low face of each cell
+  const double *faces;   // [3][3][ncell] of the low face of each cell: C alpha, the
+                         // lower cell's share of the centred IV value, signed 1 - nu_v
   const double *mom_in;  // [13][ncell] E, F(3), P(6), 3vJ(3) of I^n
   double *mom_out;       // [13][ncell] of I^{n+1}
   double *oE, *oF, *oP;  // optional copies of the new moments
@@ -106,6 +123,20 @@ __device__ __forceinline__ double fixed_ghost(const StepArgs &p, int d, int side
   return f[(size_t)m * (size_t)(p.ncell / p.n[d]) + fi];
 }
 
+// The IV value of the face between a lower cell L and an upper cell U
+// (Section 4.2: IV is advected at the flow speed u of the face, upwinded by
+// the sign of u, centred at u = 0), written as
+//   IV* = l IV_L + (1 - l) IV_U + f q_up,
+// with l = 1 (u > 0), 0 (u < 0) or 1/2 (u = 0), f = sign(u) (1 - |u| dt/dx)
+// and q_up half the van Leer slope of the upwind cell.
+__device__ __forceinline__ double iv_lower_share(double u) {
+  return u > 0.0 ? 1.0 : (u < 0.0 ? 0.0 : 0.5);
+}
+__device__ __forceinline__ double iv_signed_factor(double u, double dt_dx) {
+  const double h = 1.0 - fabs(u) * dt_dx;
+  return u > 0.0 ? h : (u < 0.0 ? -h : 0.0);
+}
+
 __device__ __forceinline__ double alpha_of(double sigma, double dl10) {
   const double s = dl10 * sigma;
   const double tau = s * s;
@@ -120,6 +151,23 @@ __device__ __forceinline__ int xcd_block(int b, int nb) {
   const int q = nb / 8;
   if (b >= 8 * q) return b;
   return (b % 8) * q + b / 8;
+}
+
+// Tile of block b for stencil reuse in L2: each XCD takes a contiguous slab
+// of nz/8 z-planes, and inside its slab the z-planes vary fastest, so that
+// the tiles above, below, in front and behind a tile (its stencil
+// neighbours along y and z) run on the same XCD within a few tens of blocks
+// of it.  Grids whose planes do not hold whole tiles, or with fewer than 8
+// planes, take the XCD-contiguous order.
+__device__ __forceinline__ int slab_block(int b, int nb, const int (&n)[3]) {
+  const int plane = n[0] * n[1];
+  if (n[2] < 8 || (n[2] & 7) || (plane & 63)) return xcd_block(b, nb);
+  const int pt = plane >> 6;           // tiles per z-plane
+  const int zc = n[2] >> 3;            // z-planes per XCD slab
+  const int pos = (b & 7) * (nb >> 3) + (b >> 3);
+  const int slab = pos / (zc * pt), r = pos - slab * (zc * pt);
+  const int z = slab * zc + r % zc;
+  return z * pt + r / zc;
 }
 
 __device__ __forceinline__ double wave_sum(double x) {

@@ -70,6 +70,9 @@ struct rt_ctx {
   // own allocation owned by the context
   double *d_gface[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
   float *d_muf = nullptr, *d_wf = nullptr;
+  int nrec = 0;                         // angle records (nang, padded to the kernel's slots)
+  double *d_arec = nullptr;             // [nrec][kRec] per-call angle records
+  float *d_arecf = nullptr;
   void *I[2] = {nullptr, nullptr};
   int cur = 0;
   double *mom[2] = {nullptr, nullptr};  // [13][ncell]: E, F, P, 3vJ

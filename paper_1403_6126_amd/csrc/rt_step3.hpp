@@ -8,9 +8,10 @@
 // direction of every axis are scalars, and every intensity load reads 64
 // consecutive cells of one angle plane.  Per step:
 //   phase A  transport increment of the wave's angles (Section 4.2), one
-//            active axis at a time, from a per-call interface table (alpha,
-//            flow speed, IV Courant factor) and 3 v J carried with the
-//            moments;
+//            active axis at a time: the flux difference of the two faces
+//            from the differences of I~ and IV between consecutive stencil
+//            cells, with a per-call interface table (C alpha, IV upwinding)
+//            and per-angle factors (mu_d dt/dx, 1 - nu) read as scalars;
 //   phase B  the absorption right-hand side r4 and the wave's partial sums of
 //            the per-cell sums of the reduced absorption and scattering
 //            systems; the per-angle values stay in registers;
@@ -31,36 +32,51 @@ namespace rtk {
 constexpr int kNsum = 22;        // per-cell sums of phase B
 constexpr int kChunk = 11;       // values reduced per LDS round
 
-// up1 + (h2/2) * vanLeer(up1 - up2, dn1 - up1), vanLeer(a, b) = 2ab/(a + b)
-// when ab > 0, else 0: the upwind interface value of the monotonic
-// piecewise-linear reconstruction at Courant number nu, h2 = 1 - nu.  The
-// factor 2 of the limiter and the 1/2 of the Courant factor cancel exactly
-// (scaling by 2 is exact), which saves an instruction per face.
+// Half the van Leer harmonic-mean slope of two consecutive differences:
+// ab/(a + b) when ab > 0, else 0 (zero at extrema).  The upwind interface
+// value of the monotonic piecewise-linear reconstruction at Courant number
+// nu is the upwind cell's value plus (1 - nu) times this, signed by the
+// direction.  It is symmetric in a and b, and odd under a, b -> -a, -b.
 template <typename A>
-__device__ __forceinline__ A vl_face(A up2, A up1, A dn1, A h2) {
-  const A a = up1 - up2, b = dn1 - up1;
+__device__ __forceinline__ A vl_half(A a, A b) {
   const A ab = a * b;
   const A q = ab * limiter_rcp(a + b);
-  return up1 + h2 * (ab > A(0) ? q : A(0));
+  return ab > A(0) ? q : A(0);
 }
 
-// Stencil of one cell along one axis.
+// Transport data of one cell along one axis, shared by every angle slot of
+// the wave (loaded once per axis).
+//
+// The flux difference of a cell needs the intensities of the cells -2..+2
+// only through their consecutive differences: with D_k the differences of
+// I~ = I - IV/C between cells -2|-1, -1|0, 0|+1, +1|+2 (k = 0..3), the
+// alpha-blend of the two faces (Section 4.2) gives, for mu_d > 0,
+//   x_R - x_L = Cb_R D_2 + (Ca_L + Cb_L) D_1 + h2 (Ca_R q_0 - Ca_L q_-1),
+// and for mu_d < 0
+//   x_R - x_L = (Ca_R + Cb_R) D_2 + Cb_L D_1 - h2 (Ca_R q_+1 - Ca_L q_0),
+// Ca = C alpha, Cb = C (1 - alpha)/2, h2 = 1 - nu, q the half slopes of
+// I~; the cell's own C I~ cancels between the faces (Ca + 2 Cb = C).  The
+// IV values of the two faces likewise differ by
+//   (1 - l_R) V_2 + l_L V_1 + f_R qv_R - f_L qv_L,
+// V_k the differences of IV = n.W (W = 3 v J) and qv the half slope of the
+// face's upwind cell.
 template <typename A>
-struct Stencil {
-  int idx[4];   // cells at offsets -2, -1, +1, +2 (wrapped, or the edge cell)
-  int kind[4];  // 0 read the cell, 1 fixed table, 2 vacuum
-  A wv[4][3];   // 3 v J at those cells
-  A aL, aR, hL, hR;  // hL, hR: 1 - nu of the IV faces (twice the table's)
-  A bL, bR;          // (1 - alpha)/2: the weight of the sum of the two centre values
-  double uL, uR;
+struct AxisData {
+  unsigned idx[4];  // cells at offsets -2, -1, +1, +2 (wrapped, or the edge cell)
+  int kind[4];      // 0 read the cell, 1 fixed table, 2 vacuum
+  A dW[4][3];       // W(-1)-W(-2), W(0)-W(-1), W(+1)-W(0), W(+2)-W(+1)
+  A caL, cbL, caR, cbR;
+  A lL, rR;         // l of the low face, 1 - l of the high face
+  A fL, fR;         // signed IV slope factors of the two faces
 };
 
 template <typename A, bool PER>
-__device__ __forceinline__ void load_stencil(const StepArgs &p, int c, const int q[3], int d,
-                                             Stencil<A> &s) {
+__device__ __forceinline__ void load_axis(const StepArgs &p, int c, const int q[3], int d,
+                                          const A (&Wc)[3], AxisData<A> &s) {
   const int n = p.n[d];
   const size_t N = (size_t)p.ncell;
   const int offs[4] = {-2, -1, 1, 2};
+  A W[4][3];
 #pragma unroll
   for (int j = 0; j < 4; ++j) {
     const int k = q[d] + offs[j];
@@ -75,31 +91,56 @@ __device__ __forceinline__ void load_stencil(const StepArgs &p, int c, const int
       }
     }
     const int cj = c + (kk - q[d]) * p.stride[d];
-    s.idx[j] = cj;
+    s.idx[j] = (unsigned)cj;
     s.kind[j] = kind;
 #pragma unroll
-    for (int t = 0; t < 3; ++t) s.wv[j][t] = A(p.mom_in[(size_t)(10 + t) * N + cj]);
+    for (int t = 0; t < 3; ++t) W[j][t] = A(p.mom_in[(size_t)(10 + t) * N + cj]);
   }
-  s.aL = A(p.faces[(size_t)(d * 3 + 0) * N + c]);
-  s.hL = A(p.faces[(size_t)(d * 3 + 1) * N + c]);
-  s.hL += s.hL;
-  s.uL = p.faces[(size_t)(d * 3 + 2) * N + c];
+#pragma unroll
+  for (int t = 0; t < 3; ++t) {
+    s.dW[0][t] = W[1][t] - W[0][t];
+    s.dW[1][t] = Wc[t] - W[1][t];
+    s.dW[2][t] = W[2][t] - Wc[t];
+    s.dW[3][t] = W[3][t] - W[2][t];
+  }
+  const A hC = A(0.5 * p.C);
+  s.caL = A(p.faces[(size_t)(d * 3 + 0) * N + c]);
+  s.lL = A(p.faces[(size_t)(d * 3 + 1) * N + c]);
+  s.fL = A(p.faces[(size_t)(d * 3 + 2) * N + c]);
   if (PER || q[d] + 1 < n || p.bc[d][1] == kPeriodic) {
-    const int cr = s.idx[2];
-    s.aR = A(p.faces[(size_t)(d * 3 + 0) * N + cr]);
-    s.hR = A(p.faces[(size_t)(d * 3 + 1) * N + cr]);
-    s.hR += s.hR;
-    s.uR = p.faces[(size_t)(d * 3 + 2) * N + cr];
+    const unsigned cr = s.idx[2];
+    s.caR = A(p.faces[(size_t)(d * 3 + 0) * N + cr]);
+    s.rR = A(1.0 - p.faces[(size_t)(d * 3 + 1) * N + cr]);
+    s.fR = A(p.faces[(size_t)(d * 3 + 2) * N + cr]);
   } else {
     // high non-periodic boundary: the ghost copies this cell's fields
     const double u = p.v[(size_t)d * N + c];
-    s.aR = A(alpha_of(p.sa[c] + p.ss[c], p.dl10[d]));
-    s.hR = A(0.5 * (1.0 - fabs(u) * p.dt_dx[d]));
-    s.hR += s.hR;
-    s.uR = u;
+    s.caR = A(p.C * alpha_of(p.sa[c] + p.ss[c], p.dl10[d]));
+    s.rR = A(1.0 - iv_lower_share(u));
+    s.fR = A(iv_signed_factor(u, p.dt_dx[d]));
   }
-  s.bL = A(0.5) * (A(1) - s.aL);
-  s.bR = A(0.5) * (A(1) - s.aR);
+  s.cbL = hC - A(0.5) * s.caL;
+  s.cbR = hC - A(0.5) * s.caR;
+  // dt/dx_d taken into the face coefficients: the increment is then
+  // -mu_d times the sum they weight
+  const A dtdx = A(p.dt_dx[d]);
+  s.caL *= dtdx;
+  s.cbL *= dtdx;
+  s.caR *= dtdx;
+  s.cbR *= dtdx;
+  s.lL *= dtdx;
+  s.rR *= dtdx;
+  s.fL *= dtdx;
+  s.fR *= dtdx;
+}
+
+// Element idx of an angle plane, addressed by a 32-bit byte offset from the
+// wave-uniform start of the plane (one scalar base and one vector register
+// per load).  rt_create keeps every plane below 4 GiB.
+template <typename S>
+__device__ __forceinline__ S plane_ld(const S *plane, unsigned idx) {
+  const unsigned off = idx * (unsigned)sizeof(S);
+  return *reinterpret_cast<const S *>(reinterpret_cast<const char *>(plane) + off);
 }
 
 // Intensity at a stencil cell from the value raw read at its (clamped) cell
@@ -130,10 +171,13 @@ __device__ __forceinline__ void waves_reduce(double (&x)[NV], double *buf, doubl
     __syncthreads();
     for (int v = g; v < nr; v += G) {
       double s = buf[v * 64 + lane];
-      const bool mn = MINLAST && r0 + v == NV - 1;
-      for (int j = 1; j < G; ++j) {
-        const double y = buf[(j * R + v) * 64 + lane];
-        s = mn ? fmin(s, y) : s + y;
+      if (MINLAST && r0 + v == NV - 1) {  // wave-uniform branch
+        for (int j = 1; j < G; ++j) {
+          const double y = buf[(j * R + v) * 64 + lane];
+          s = y < s ? y : s;
+        }
+      } else {
+        for (int j = 1; j < G; ++j) s += buf[(j * R + v) * 64 + lane];
       }
       tot[v * 64 + lane] = s;
     }
@@ -166,10 +210,14 @@ __device__ __forceinline__ void stream_store(T *p, T v) {
     *p = v;
 }
 
+// FP64 slots with one angle group keep the cell's intensities in LDS.
+#ifndef RT_IC_LDS
+#define RT_IC_LDS 0
+#endif
 // Slots whose plane reads are in flight ahead of the transport arithmetic
 // (FP64 storage: one, as registers allow).
 #ifndef RT_PREFETCH_F64
-#define RT_PREFETCH_F64 1
+#define RT_PREFETCH_F64 2
 #endif
 #ifndef RT_PREFETCH_F32
 #define RT_PREFETCH_F32 3
@@ -183,6 +231,15 @@ __device__ __forceinline__ A tab(const double *d, const float *f, int i) {
     return f[i];
   else
     return d[i];
+}
+
+// The record of angle m (StepArgs::arec) in the arithmetic type.
+template <typename A>
+__device__ __forceinline__ const A *angle_rec(const StepArgs &p, int m) {
+  if constexpr (sizeof(A) == 4)
+    return p.arecf + (size_t)m * kRec;
+  else
+    return p.arec + (size_t)m * kRec;
 }
 
 // Shared memory of one step body.
@@ -214,102 +271,121 @@ __device__ __forceinline__ void step3_tile(const StepArgs &p, int blk, int G, St
   const size_t N = (size_t)p.ncell;
   const S *Iin = static_cast<const S *>(p.I_in);
   S *Iout = static_cast<S *>(p.I_out);
-  const double C = p.C, P = p.P, dt = p.dt;
-  // angle of a slot (wave-uniform); valid when < NA, table reads clamped
-  auto slot_m = [&](int s) { return (g + (s / KA) * G) * KA + (s % KA); };
+  const double C = p.C, P = p.P, dt = p.dt, iC = p.invC;
+  // angle of a slot (wave-uniform), m0 + slot_off(s): valid when < NA.  The
+  // slot's angle record and intensity plane are offsets from the wave's
+  // first (constant offsets when the wave has one group).
+  const int m0 = g * KA;
+  auto slot_off = [&](int s) { return (s / KA) * G * KA + (s % KA); };
+  auto slot_m = [&](int s) { return m0 + slot_off(s); };
+  const A *Rg = angle_rec<A>(p, m0);
+  const double *Rgd = p.arec + (size_t)m0 * kRec;
+  const S *Ig = Iin + (size_t)m0 * N;
+  S *Og = Iout + (size_t)m0 * N;
+  auto slot_rec = [&](int s) { return Rg + (unsigned)slot_off(s) * kRec; };
+  auto slot_plane = [&](int s) { return Ig + (size_t)(unsigned)slot_off(s) * N; };
 
   // ------------------------------------------------ phase A: transport
-  A Ic[NS], dF[NS];
+  // The cell's intensities of the wave's slots: in registers, or (FP64 with
+  // one angle group) in the wave's own rows of the reduction buffer, which
+  // phase B's reduction overwrites only after the wave has read them.  The
+  // LDS copy leaves the registers to the transport's stencil data; its
+  // address is made opaque per use site so that each site reloads it.
+  constexpr bool IC_LDS = RT_IC_LDS && sizeof(A) == 8 && NS <= kChunk;
+  A Ic[IC_LDS ? 1 : NS], dF[NS];
+  double *icl = sbuf + (size_t)g * kChunk * 64 + lane;
+  auto icv = [&](int k) -> A {
+    if constexpr (IC_LDS) {
+      return A(icl[k * 64]);
+    } else {
+      return Ic[k];
+    }
+  };
+  auto ic_fence = [&]() {
+    if constexpr (IC_LDS) asm volatile("" : "+v"(icl));
+  };
 #pragma unroll
   for (int s = 0; s < NS; ++s) {
     const int m = slot_m(s);
-    Ic[s] = m < NA ? A(Iin[(size_t)m * N + c]) : A(0);
+    const A v = m < NA ? A(plane_ld(slot_plane(s), (unsigned)c)) : A(0);
+    if constexpr (IC_LDS)
+      icl[s * 64] = double(v);
+    else
+      Ic[s] = v;
     dF[s] = A(0);
   }
   if (FUSED) {
     const int q[3] = {c % p.n[0], (c / p.n[0]) % p.n[1], c / (p.n[0] * p.n[1])};
-    const A wc0 = A(p.mom_in[10 * N + c]), wc1 = A(p.mom_in[11 * N + c]),
-            wc2 = A(p.mom_in[12 * N + c]);
-    const A AC = A(C), invC = A(p.invC);
+    const A Wc[3] = {A(p.mom_in[10 * N + c]), A(p.mom_in[11 * N + c]), A(p.mom_in[12 * N + c])};
+    const A invC = A(p.invC);
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
       if (d >= p.ndim) break;
-      Stencil<A> s;
-      load_stencil<A, PER>(p, c, q, d, s);
-      const A dtdx = A(p.dt_dx[d]);
-      const bool posR = s.uR > 0.0, posL = s.uL > 0.0;
-      const bool zeroR = s.uR == 0.0, zeroL = s.uL == 0.0;
+      AxisData<A> s;
+      load_axis<A, PER>(p, c, q, d, Wc, s);
+      ic_fence();
       constexpr int UNR = sizeof(A) == 8 ? RT_UNROLL_F64 : RT_UNROLL_F32;
       // the plane reads of a slot: cells -1 and +1 and the far upwind cell
       // (-2 for mu_d > 0, else +2).  Those of the PF next slots are issued
       // before the arithmetic of the current one, so that their latency
       // overlaps it.
       auto reads = [&](int k, S (&r)[3]) {
-        const int m = slot_m(k);
-        const int mc = m < NA ? m : NA - 1;
-        const S *Im = Iin + (size_t)mc * N;
-        r[0] = Im[s.idx[1]];
-        r[1] = Im[s.idx[2]];
-        r[2] = Im[tab<A>(p.mu, p.muf, d * NA + mc) > A(0) ? s.idx[0] : s.idx[3]];
+        if (slot_m(k) < NA) {
+          const S *Im = slot_plane(k);
+          r[0] = plane_ld(Im, s.idx[1]);
+          r[1] = plane_ld(Im, s.idx[2]);
+          r[2] = plane_ld(Im, slot_rec(k)[rec_n0 + d] > A(0) ? s.idx[0] : s.idx[3]);
+        } else {
+          r[0] = r[1] = r[2] = S(0);
+        }
       };
       constexpr int PF = sizeof(A) == 8 ? RT_PREFETCH_F64 : RT_PREFETCH_F32;
-      S q[PF][3];
+      S rq[PF][3];
 #pragma unroll
       for (int j = 0; j < PF; ++j)
-        if (j < NS) reads(j, q[j]);
+        if (j < NS) reads(j, rq[j]);
 #pragma unroll UNR
       for (int k = 0; k < NS; ++k) {
-          S r[3];
+        S r[3];
 #pragma unroll
-          for (int t = 0; t < 3; ++t) r[t] = q[0][t];
+        for (int t = 0; t < 3; ++t) r[t] = rq[0][t];
 #pragma unroll
-          for (int j = 0; j + 1 < PF; ++j)
+        for (int j = 0; j + 1 < PF; ++j)
 #pragma unroll
-            for (int t = 0; t < 3; ++t) q[j][t] = q[j + 1][t];
-          if (k + PF < NS) reads(k + PF, q[PF - 1]);
-          const int m = slot_m(k);
-          const int mc = m < NA ? m : NA - 1;
-          const A n0 = tab<A>(p.mu, p.muf, mc), n1 = tab<A>(p.mu, p.muf, NA + mc),
-                  n2 = tab<A>(p.mu, p.muf, 2 * NA + mc);
-          const A mud = d == 0 ? n0 : d == 1 ? n1 : n2;
-          if (m < NA && mud != A(0)) {  // uniform over the wave
-          A IV[4];
+          for (int t = 0; t < 3; ++t) rq[j][t] = rq[j + 1][t];
+        if (k + PF < NS) reads(k + PF, rq[PF - 1]);
+        const int m = slot_m(k);
+        const A *R = slot_rec(k);  // padding slots: zero records
+        const A mud = R[rec_n0 + d];
+        if (m < NA && mud != A(0)) {  // uniform over the wave
+          const A n0 = R[rec_n0], n1 = R[rec_n1], n2 = R[rec_n2];
+          const A h2 = R[rec_h0 + d];  // 1 - nu
+          // differences of IV = n.W between consecutive stencil cells
+          A V[4];
 #pragma unroll
-          for (int j = 0; j < 4; ++j) IV[j] = n0 * s.wv[j][0] + n1 * s.wv[j][1] + n2 * s.wv[j][2];
-          const A IVc = n0 * wc0 + n1 * wc1 + n2 * wc2;
-          const A Itc = Ic[k] - IVc * invC;
+          for (int j = 0; j < 4; ++j) V[j] = n0 * s.dW[j][0] + n1 * s.dW[j][1] + n2 * s.dW[j][2];
           const A Im1 = plane_value<S, A, PER>(p, r[0], s.idx[1], s.kind[1], 0, d, m, mud);
           const A Ip1 = plane_value<S, A, PER>(p, r[1], s.idx[2], s.kind[2], 1, d, m, mud);
-          const A Itm1 = Im1 - IV[1] * invC, Itp1 = Ip1 - IV[2] * invC;
-          const A h = A(1) - AC * fabs(mud) * dtdx;  // 1 - nu
-          A upR, upL;
+          const A ick = icv(k);
+          const A D1 = (ick - Im1) - V[1] * invC;
+          const A D2 = (Ip1 - ick) - V[2] * invC;
+          A T;
           if (mud > A(0)) {
             const A Im2 = plane_value<S, A, PER>(p, r[2], s.idx[0], s.kind[0], 0, d, m, mud);
-            const A Itm2 = Im2 - IV[0] * invC;
-            upR = vl_face(Itm1, Itc, Itp1, h);
-            upL = vl_face(Itm2, Itm1, Itc, h);
+            const A D0 = (Im1 - Im2) - V[0] * invC;
+            const A qm = vl_half(D0, D1), q0 = vl_half(D1, D2);
+            T = s.cbR * D2 + (s.caL + s.cbL) * D1 + h2 * (s.caR * q0 - s.caL * qm);
           } else {
             const A Ip2 = plane_value<S, A, PER>(p, r[2], s.idx[3], s.kind[3], 1, d, m, mud);
-            const A Itp2 = Ip2 - IV[3] * invC;
-            upR = vl_face(Itp2, Itp1, Itc, h);
-            upL = vl_face(Itp1, Itc, Itm1, h);
+            const A D3 = (Ip2 - Ip1) - V[3] * invC;
+            const A q0 = vl_half(D1, D2), qp = vl_half(D2, D3);
+            T = (s.caR + s.cbR) * D2 + s.cbL * D1 - h2 * (s.caR * qp - s.caL * q0);
           }
-          // alpha I~*_up + (1 - alpha) I~_c of the two faces
-          const A xR = s.aR * upR + s.bR * (Itc + Itp1);
-          const A xL = s.aL * upL + s.bL * (Itm1 + Itc);
-          A ivR, ivL;
-          {
-            const A u2 = posR ? IV[1] : IV[3], u1 = posR ? IVc : IV[2], d1 = posR ? IV[2] : IVc;
-            const A f = vl_face(u2, u1, d1, s.hR);
-            ivR = zeroR ? A(0.5) * (IVc + IV[2]) : f;
-          }
-          {
-            const A u2 = posL ? IV[0] : IV[2], u1 = posL ? IV[1] : IVc, d1 = posL ? IVc : IV[1];
-            const A f = vl_face(u2, u1, d1, s.hL);
-            ivL = zeroL ? A(0.5) * (IV[1] + IVc) : f;
-          }
-          // the fluxes C mu x + mu IV* with mu dt/dx taken out of the difference
-          dF[k] -= (dtdx * mud) * ((AC * xR + ivR) - (AC * xL + ivL));
+          // IV faces: the upwind cell of each face by the sign of its flow
+          const A qvL = vl_half(s.fL > A(0) ? V[0] : V[2], V[1]);
+          const A qvR = vl_half(s.fR > A(0) ? V[1] : V[3], V[2]);
+          T += s.rR * V[2] + s.lL * V[1] + (s.fR * qvR - s.fL * qvL);
+          dF[k] -= mud * T;
         }
       }
     }
@@ -337,9 +413,10 @@ __device__ __forceinline__ void step3_tile(const StepArgs &p, int blk, int G, St
     const double F0 = p.mom_in[N + c], F1 = p.mom_in[2 * N + c], F2 = p.mom_in[3 * N + c];
     const double P0 = p.mom_in[4 * N + c], P1 = p.mom_in[5 * N + c], P2 = p.mom_in[6 * N + c];
     const double base = rho + h * C * rho;
-    u0 = (rho * v0 + h * (C * rho * v0 + P * F0)) / (base + h * P * (E + P0) / C);
-    u1 = (rho * v1 + h * (C * rho * v1 + P * F1)) / (base + h * P * (E + P1) / C);
-    u2 = (rho * v2 + h * (C * rho * v2 + P * F2)) / (base + h * P * (E + P2) / C);
+    const double hPC = h * P * iC;
+    u0 = (rho * v0 + h * (C * rho * v0 + P * F0)) * fast_rcp(base + hPC * (E + P0));
+    u1 = (rho * v1 + h * (C * rho * v1 + P * F1)) * fast_rcp(base + hPC * (E + P1));
+    u2 = (rho * v2 + h * (C * rho * v2 + P * F2)) * fast_rcp(base + hPC * (E + P2));
   }
   const double uu = u0 * u0 + u1 * u1 + u2 * u2;
   const bool to5 = ss > sa;  // Step 2 routing
@@ -348,19 +425,22 @@ __device__ __forceinline__ void step3_tile(const StepArgs &p, int blk, int G, St
   const A Au0 = A(u0), Au1 = A(u1), Au2 = A(u2), Auu = A(uu);
   const A dsa = A(dt * sa), dss = A(dt * ss);
   const A D0 = A(1.0 + dt * sa * C), E0 = A(dt * sa * C), AW0 = A(1.0 + dt * C * ss);
-  const A B0 = A(-dt * C * ss - dt * ss * uu / C), dssC = A(dt * ss / C);
+  const A B0 = A(-dt * C * ss - dt * ss * uu * iC), dssC = A(dt * ss * iC);
+  // the routing as factors: r4 = I + g4 dF, p = r4/D + g5 dF
+  const A g4 = to5 ? A(0) : A(1), g5 = to5 ? A(1) : A(0);
   A pk[NS];
   A sm[kNsum];
 #pragma unroll
   for (int r = 0; r < kNsum; ++r) sm[r] = A(0);
+  ic_fence();
 #pragma unroll
   for (int k = 0; k < NS; ++k) {
     pk[k] = A(0);
     const int m = slot_m(k);
     if (m >= NA) continue;
-    const A n0 = tab<A>(p.mu, p.muf, m), n1 = tab<A>(p.mu, p.muf, NA + m),
-            n2 = tab<A>(p.mu, p.muf, 2 * NA + m);
-    const A Wm = tab<A>(p.w, p.wf, m);
+    const A *R = slot_rec(k);
+    const A n0 = R[rec_n0], n1 = R[rec_n1], n2 = R[rec_n2];
+    const A Wm = R[rec_w];
     const A t = n0 * Au0 + n1 * Au1 + n2 * Au2;
     const A D = D0 - dsa * t, aw = AW0 - dss * t;
     const A rDa = fast_rcp(D * aw);
@@ -369,8 +449,9 @@ __device__ __forceinline__ void step3_tile(const StepArgs &p, int blk, int G, St
     const A gg = Auu + t * t;
     const A b = B0 + A(2) * dss * t - dssC * t * t;
     const A cm = A(-3) * dss * t;
-    const A r4 = to5 ? Ic[k] : Ic[k] + dF[k];
-    const A pm = r4 * invD + (to5 ? dF[k] : A(0));
+    const A ick = icv(k);
+    const A r4 = ick + g4 * dF[k];
+    const A pm = r4 * invD + g5 * dF[k];
     pk[k] = pm;
     const A WD = Wm * invD, Wa = Wm * invaw, Wad = Wa * invD;
     sm[0] += WD * r4;
@@ -392,10 +473,10 @@ __device__ __forceinline__ void step3_tile(const StepArgs &p, int blk, int G, St
     sm[16] += Wad * b;
     sm[17] += Wad * e;
     sm[18] += Wad;
-    const A WI = Wm * (Ic[k] + dF[k]);
-    sm[19] += n0 * WI;
-    sm[20] += n1 * WI;
-    sm[21] += n2 * WI;
+    const A Ir = ick + dF[k];
+    sm[19] += R[rec_wn0] * Ir;
+    sm[20] += R[rec_wn1] * Ir;
+    sm[21] += R[rec_wn2] * Ir;
   }
   double Sa[kChunk], Sb[kChunk];
 #pragma unroll
@@ -408,24 +489,25 @@ __device__ __forceinline__ void step3_tile(const StepArgs &p, int blk, int G, St
   // Sa = sums 0..10, Sb = sums 11..21
 
   // --------------------------------------------- solve (FP64, wave 0)
-  const double kap = dt * sa / C;
+  const double kap = dt * sa * iC;
   const double cv = rho * p.cvfac;
   if (g == 0) {
     const double qden = 1.0 + kap * Sa[8];
-    const double q0 = Sa[6] / qden, q1 = Sa[7] / qden;
+    const double iqden = fast_rcp(qden);
+    const double q0 = Sa[6] * iqden, q1 = Sa[7] * iqden;
     const double j0 = Sa[0] - kap * Sa[2] * q0, j1 = Sa[1] - kap * Sa[2] * q1;
     const double k0 = Sa[3] - kap * Sa[5] * q0, k1 = Sa[4] - kap * Sa[5] * q1;
     const double beta = P * C * (1.0 - uu / (C * C)) * sa * dt;
     const double g8 = 8.0 * kPi * P * sa * dt;
-    const double h0 = -g8 * (k0 - q0 / C) + kFourPi * beta * j0;
-    const double h1q = (-g8 * (k1 - q1 / C) - kFourPi * beta * (1.0 - j1)) * (1.0 / kFourPi);
+    const double h0 = -g8 * (k0 - q0 * iC) + kFourPi * beta * j0;
+    const double h1q = (-g8 * (k1 - q1 * iC) - kFourPi * beta * (1.0 - j1)) * (1.0 / kFourPi);
     double T = Tn;
     int it;
     bool conv = false;
     for (it = 1; it <= p.maxit; ++it) {
       const double T3 = T * T * T;
       const double f = cv * (T - Tn) - h0 - h1q * T3 * T;
-      const double dT = f / (cv - 4.0 * h1q * T3);
+      const double dT = f * fast_rcp(cv - 4.0 * h1q * T3);
       T -= dT;
       if (fabs(dT) <= p.rtol * fabs(T)) {
         conv = true;
@@ -441,8 +523,9 @@ __device__ __forceinline__ void step3_tile(const StepArgs &p, int blk, int G, St
     const double det = a11 * a22 - a12 * a21;
     ssol[0 * 64 + lane] = X;
     ssol[1 * 64 + lane] = kap * Q;
-    ssol[2 * 64 + lane] = (Sbr * a22 - a12 * Sr5) / det;
-    ssol[3 * 64 + lane] = (a11 * Sr5 - a21 * Sbr) / det;
+    const double idet = fast_rcp(det);
+    ssol[2 * 64 + lane] = (Sbr * a22 - a12 * Sr5) * idet;
+    ssol[3 * 64 + lane] = (a11 * Sr5 - a21 * Sbr) * idet;
     ssol[4 * 64 + lane] = T;
     ssol[5 * 64 + lane] = double(it);
   }
@@ -461,28 +544,20 @@ __device__ __forceinline__ void step3_tile(const StepArgs &p, int blk, int G, St
   for (int k = 0; k < NS; ++k) {
     const int m = slot_m(k);
     if (m >= NA) continue;
-    const double d0 = p.mu[m], d1 = p.mu[NA + m], d2 = p.mu[2 * NA + m];
-    const A t = tab<A>(p.mu, p.muf, m) * Au0 + tab<A>(p.mu, p.muf, NA + m) * Au1 +
-                tab<A>(p.mu, p.muf, 2 * NA + m) * Au2;
+    const A *R = slot_rec(k);
+    const A t = R[rec_n0] * Au0 + R[rec_n1] * Au1 + R[rec_n2] * Au2;
     const A D = D0 - dsa * t, aw = AW0 - dss * t;
     const A rDa = fast_rcp(D * aw);
     const A e = E0 + A(3) * dsa * t;
     const A cm = A(-3) * dss * t;
     // I' = invaw (p - s1 - c s2) + invD invaw (e X - kappa Q)
     const S Inew = S(D * rDa * (pk[k] - As1 - cm * As2) + rDa * (e * AX - AkQ));
-    if (act) stream_store(&Iout[(size_t)m * N + c], Inew);
-    const double Iw = double(Inew) * p.w[m];
-    mo[0] += Iw;
-    mo[1] += d0 * Iw;
-    mo[2] += d1 * Iw;
-    mo[3] += d2 * Iw;
-    mo[4] += d0 * d0 * Iw;
-    mo[5] += d1 * d1 * Iw;
-    mo[6] += d2 * d2 * Iw;
-    mo[7] += d0 * d1 * Iw;
-    mo[8] += d0 * d2 * Iw;
-    mo[9] += d1 * d2 * Iw;
-    mo[10] = fmin(mo[10], double(Inew));
+    if (act) stream_store(&Og[(size_t)(unsigned)slot_off(k) * N + c], Inew);
+    // the quadrature of Section 3: w, w n_i and w n_i n_j from the table
+    const double In = double(Inew);
+#pragma unroll
+    for (int r = 0; r < 10; ++r) mo[r] += Rgd[(unsigned)slot_off(k) * kRec + rec_w + r] * In;
+    mo[10] = In < mo[10] ? In : mo[10];
   }
   waves_reduce<kChunk, true, Step3Smem<S>::R>(mo, sbuf, stot, g, G, lane);
 #pragma unroll
@@ -491,22 +566,23 @@ __device__ __forceinline__ void step3_tile(const StepArgs &p, int blk, int G, St
   // ------------------------------------------------ Step 7 and outputs
   // the gas changes: gasfac (C over the reduced speed, 1 without one) times
   // the momentum the radiation loses, and the true heat capacity
-  const double f4 = kFourPi * P / C, gf = p.gasfac;
-  const double dm0 = gf * (-(P / C) * mo[1] + f4 * Sb[8]);
-  const double dm1 = gf * (-(P / C) * mo[2] + f4 * Sb[9]);
-  const double dm2 = gf * (-(P / C) * mo[3] + f4 * Sb[10]);
+  const double PC = P * iC, f4 = kFourPi * PC, gf = p.gasfac;
+  const double irho = fast_rcp(rho);
+  const double dm0 = gf * (-PC * mo[1] + f4 * Sb[8]);
+  const double dm1 = gf * (-PC * mo[2] + f4 * Sb[9]);
+  const double dm2 = gf * (-PC * mo[3] + f4 * Sb[10]);
   const double mm0 = rho * v0, mm1 = rho * v1, mm2 = rho * v2;
   const double ek =
       (((mm0 + dm0) * (mm0 + dm0) + (mm1 + dm1) * (mm1 + dm1) + (mm2 + dm2) * (mm2 + dm2)) -
-       (mm0 * mm0 + mm1 * mm1 + mm2 * mm2)) /
-      (2.0 * rho);
+       (mm0 * mm0 + mm1 * mm1 + mm2 * mm2)) *
+      (0.5 * irho);
   const double cvg = cv * gf;
   const double deg = cvg * (T - Tn) + ek;
   // gas feedback (rho fixed): the momentum change of the step moves the flow;
   // 3 v J of the new state, used by the next step's IV, takes the new v
-  const double vn0 = p.feedback ? v0 + dm0 / rho : v0;
-  const double vn1 = p.feedback ? v1 + dm1 / rho : v1;
-  const double vn2 = p.feedback ? v2 + dm2 / rho : v2;
+  const double vn0 = p.feedback ? v0 + dm0 * irho : v0;
+  const double vn1 = p.feedback ? v1 + dm1 * irho : v1;
+  const double vn2 = p.feedback ? v2 + dm2 * irho : v2;
   if (act) {
     // The per-cell fields (0-9 the moments, 10-12 3vJ of the new state, 13
     // T, 14 dEgas, 15-17 dMom, 18-27 the optional output moments) are spread
@@ -575,9 +651,9 @@ __device__ __forceinline__ void step3_tile(const StepArgs &p, int blk, int G, St
     tot[4] = on ? dm0 * vol : 0.0;
     tot[5] = on ? dm1 * vol : 0.0;
     tot[6] = on ? dm2 * vol : 0.0;
-    tot[7] = on ? P / C * mo[1] * vol : 0.0;
-    tot[8] = on ? P / C * mo[2] * vol : 0.0;
-    tot[9] = on ? P / C * mo[3] * vol : 0.0;
+    tot[7] = on ? PC * mo[1] * vol : 0.0;
+    tot[8] = on ? PC * mo[2] * vol : 0.0;
+    tot[9] = on ? PC * mo[3] * vol : 0.0;
     tot[10] = on ? mo[10] : 1.0e300;
     tot[11] = on ? newton_it : 0.0;
 #pragma unroll
@@ -588,15 +664,24 @@ __device__ __forceinline__ void step3_tile(const StepArgs &p, int blk, int G, St
   }
 }
 
-// Waves per SIMD the register allocation of k_step3 targets (8-wave blocks:
-// 2 = one block per CU, 4 = two, 6 = three).  Measured on the 128^3 S8 box:
-// FP64 at 4 (128 VGPRs, a small spill) runs 5.0 ms against 6.0 ms at 2;
-// FP32 at 6 (80 VGPRs) spills enough to lose to 4.
+// Waves per SIMD the register allocation of k_step3 targets.  FP64 at 2
+// (256 VGPRs, no spill; with 4-wave blocks two blocks share a CU) measured
+// 3.9 ms on the 128^3 S8 box against 4.6-4.8 ms at 4 (128 VGPRs with a
+// 170-byte spill whose traffic dominated); FP32 at 4 does not spill.
 #ifndef RT_STEP3_WAVES_F64
-#define RT_STEP3_WAVES_F64 4
+#define RT_STEP3_WAVES_F64 2
 #endif
 #ifndef RT_STEP3_WAVES_F32
 #define RT_STEP3_WAVES_F32 4
+#endif
+
+// Order of the tiles over the blocks: 0 dispatch order, 1 XCD-contiguous,
+// 2 XCD slabs of z-planes with z fastest (slab_block).
+#ifndef RT_BLOCK_ORDER_F64
+#define RT_BLOCK_ORDER_F64 2
+#endif
+#ifndef RT_BLOCK_ORDER_F32
+#define RT_BLOCK_ORDER_F32 2
 #endif
 
 template <typename S, typename A, int KA, int NG, bool PER, bool FUSED>
@@ -604,9 +689,9 @@ __global__ __launch_bounds__(64 * kMaxWaves, sizeof(S) == 8 ? RT_STEP3_WAVES_F64
                                                             : RT_STEP3_WAVES_F32) void
 k_step3(StepArgs p) {
   __shared__ Step3Smem<S> sm_;
-  // FP32 storage gains from XCD-contiguous work; the FP64 kernel, whose
-  // traffic is mostly its own spill, measured 6 % faster in dispatch order.
-  const int blk = sizeof(S) == 4 ? xcd_block(blockIdx.x, gridDim.x) : (int)blockIdx.x;
+  constexpr int ORD = sizeof(S) == 8 ? RT_BLOCK_ORDER_F64 : RT_BLOCK_ORDER_F32;
+  const int b = (int)blockIdx.x, nb = (int)gridDim.x;
+  const int blk = ORD == 2 ? slab_block(b, nb, p.n) : ORD == 1 ? xcd_block(b, nb) : b;
   step3_tile<S, A, KA, NG, PER, FUSED>(p, blk, blockDim.x >> 6, sm_);
 }
 
