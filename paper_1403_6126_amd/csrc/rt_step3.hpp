@@ -143,6 +143,20 @@ __device__ __forceinline__ S plane_ld(const S *plane, unsigned idx) {
   return *reinterpret_cast<const S *>(reinterpret_cast<const char *>(plane) + off);
 }
 
+// The same read as a raw buffer load: the plane is a buffer resource held in
+// scalar registers, the lane's byte offset one vector register, so no vector
+// address arithmetic is needed (gfx9 resource word 3 for raw loads).
+template <typename S>
+__device__ __forceinline__ S plane_buf_ld(const S *plane, unsigned idx) {
+  const __amdgpu_buffer_rsrc_t r =
+      __builtin_amdgcn_make_buffer_rsrc(const_cast<S *>(plane), 0, 0x7fffffff, 0x00020000);
+  const unsigned off = idx * (unsigned)sizeof(S);
+  if constexpr (sizeof(S) == 8)
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
+  else
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
+}
+
 // Intensity at a stencil cell from the value raw read at its (clamped) cell
 // idx of the angle plane, with the ghost kinds.
 template <typename S, typename A, bool PER>
@@ -188,13 +202,13 @@ __device__ __forceinline__ void waves_reduce(double (&x)[NV], double *buf, doubl
   }
 }
 
-// Unrolling of the transport loop over a wave's angles: full for FP64 (all
-// loads in flight at once), none for FP32 (registers).
+// Unrolling of the transport loop over a wave's angles: full (constant slot
+// indices for the register arrays; FP32 measured 6 % faster than rolled).
 #ifndef RT_UNROLL_F64
 #define RT_UNROLL_F64 NS
 #endif
 #ifndef RT_UNROLL_F32
-#define RT_UNROLL_F32 1
+#define RT_UNROLL_F32 NS
 #endif
 // The new intensities and the per-cell outputs are written once and not read
 // again by the step: with RT_STREAM_STORES they bypass the caches as
@@ -210,9 +224,35 @@ __device__ __forceinline__ void stream_store(T *p, T v) {
     *p = v;
 }
 
-// FP64 slots with one angle group keep the cell's intensities in LDS.
-#ifndef RT_IC_LDS
-#define RT_IC_LDS 0
+// The temperature and scattering solve on every wave (1) or on wave 0 with
+// the solution passed through LDS (0).
+#ifndef RT_SOLVE_ALL
+#define RT_SOLVE_ALL 1
+#endif
+// Per-cell fields loaded before the last axis of the transport (1) or after
+// the transport (0).
+#ifndef RT_CELL_EARLY_F64
+#define RT_CELL_EARLY_F64 1
+#endif
+#ifndef RT_CELL_EARLY_F32
+#define RT_CELL_EARLY_F32 0
+#endif
+// Transport loads of padding slots and slots with mu_d = 0: skipped by a
+// wave-uniform branch (0), or issued from the last plane and weighted by the
+// zero factor (1).  Plane reads by buffer loads (1) or global loads (0).
+#ifndef RT_UNCOND_LOADS
+#define RT_UNCOND_LOADS 0
+#endif
+#ifndef RT_BUFFER_LOADS
+#define RT_BUFFER_LOADS 1
+#endif
+// The cell's intensities held in registers over the transport (1) or read
+// again per slot (0: measured 8 % slower in FP64, 4 % in FP32).
+#ifndef RT_IC_REG_F64
+#define RT_IC_REG_F64 1
+#endif
+#ifndef RT_IC_REG_F32
+#define RT_IC_REG_F32 1
 #endif
 // Slots whose plane reads are in flight ahead of the transport arithmetic
 // (FP64 storage: one, as registers allow).
@@ -242,24 +282,20 @@ __device__ __forceinline__ const A *angle_rec(const StepArgs &p, int m) {
     return p.arec + (size_t)m * kRec;
 }
 
-// Shared memory of one step body.
-// Values per reduction round: all 11 at once (the registers, not the LDS,
-// bound the blocks per CU of both storage types).
-template <typename S>
-struct Step3Smem {
-  static constexpr int R = kChunk;
-  double buf[kMaxWaves * R * 64];
-  double tot[R * 64];
-  double sol[6 * 64];
-};
+// LDS of one step body, for G waves (dynamic shared memory of the launch):
+// the cross-wave reduction rows (G*kChunk*64 doubles), the reduced values
+// (kChunk*64) and the solution passed on by wave 0 (6*64).
+__host__ __device__ constexpr size_t step3_lds_bytes(int G) {
+  return sizeof(double) * ((size_t)G * kChunk * 64 + kChunk * 64 + 6 * 64);
+}
 
 // One step for the 64 cells of tile blk (cells blk*64 + lane), G waves.
 // Writes I^{n+1}, the moments and the outputs of those cells and the tile's
 // partial totals into row blk of p.partials.
 template <typename S, typename A, int KA, int NG, bool PER, bool FUSED>
-__device__ __forceinline__ void step3_tile(const StepArgs &p, int blk, int G, Step3Smem<S> &sm_) {
+__device__ __forceinline__ void step3_tile(const StepArgs &p, int blk, int G, double *lds) {
   constexpr int NS = KA * NG;  // angle slots of a wave: slot j*KA + k
-  double *sbuf = sm_.buf, *stot = sm_.tot, *ssol = sm_.sol;
+  double *sbuf = lds, *stot = lds + (size_t)G * kChunk * 64, *ssol = stot + kChunk * 64;
   const int lane = threadIdx.x & 63;
   // wave index, made provably wave-uniform so that the angle of a slot, the
   // direction cosines and the plane offsets live in scalar registers
@@ -285,33 +321,46 @@ __device__ __forceinline__ void step3_tile(const StepArgs &p, int blk, int G, St
   auto slot_rec = [&](int s) { return Rg + (unsigned)slot_off(s) * kRec; };
   auto slot_plane = [&](int s) { return Ig + (size_t)(unsigned)slot_off(s) * N; };
 
-  // ------------------------------------------------ phase A: transport
-  // The cell's intensities of the wave's slots: in registers, or (FP64 with
-  // one angle group) in the wave's own rows of the reduction buffer, which
-  // phase B's reduction overwrites only after the wave has read them.  The
-  // LDS copy leaves the registers to the transport's stencil data; its
-  // address is made opaque per use site so that each site reloads it.
-  constexpr bool IC_LDS = RT_IC_LDS && sizeof(A) == 8 && NS <= kChunk;
-  A Ic[IC_LDS ? 1 : NS], dF[NS];
-  double *icl = sbuf + (size_t)g * kChunk * 64 + lane;
-  auto icv = [&](int k) -> A {
-    if constexpr (IC_LDS) {
-      return A(icl[k * 64]);
+  // The cell's fields and the moments of I^n used by the velocity estimate.
+  // Loaded before the transport of the last active axis (CELL_EARLY), so
+  // that their latency overlaps that axis's work, or after the transport.
+  constexpr bool CELL_EARLY = sizeof(A) == 8 ? RT_CELL_EARLY_F64 : RT_CELL_EARLY_F32;
+  struct {
+    double sa, ss, rho, Tn, v[3], E, F[3], P[3];
+  } ci;
+  auto cell_load = [&]() {
+    ci.sa = p.sa[c];
+    ci.ss = p.ss[c];
+    ci.rho = p.rho[c];
+    ci.Tn = p.T[c];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) ci.v[k] = p.v[(size_t)k * N + c];
+    if (p.estimate_v) {
+      ci.E = p.mom_in[c];
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        ci.F[k] = p.mom_in[(size_t)(1 + k) * N + c];
+        ci.P[k] = p.mom_in[(size_t)(4 + k) * N + c];
+      }
     } else {
-      return Ic[k];
+      ci.E = 0.0;
+#pragma unroll
+      for (int k = 0; k < 3; ++k) ci.F[k] = ci.P[k] = 0.0;
     }
   };
-  auto ic_fence = [&]() {
-    if constexpr (IC_LDS) asm volatile("" : "+v"(icl));
-  };
+
+  // ------------------------------------------------ phase A: transport
+  // The cell's intensities of the wave's slots: held in registers (IC_REG),
+  // or read again with each slot's stencil reads (they are in L1), which
+  // leaves the registers to the transport.
+  constexpr bool IC_REG = sizeof(A) == 8 ? RT_IC_REG_F64 : RT_IC_REG_F32;
+  A Ic[IC_REG ? NS : 1], dF[NS];
 #pragma unroll
   for (int s = 0; s < NS; ++s) {
-    const int m = slot_m(s);
-    const A v = m < NA ? A(plane_ld(slot_plane(s), (unsigned)c)) : A(0);
-    if constexpr (IC_LDS)
-      icl[s * 64] = double(v);
-    else
-      Ic[s] = v;
+    if constexpr (IC_REG) {
+      const int m = slot_m(s);
+      Ic[s] = m < NA ? A(plane_ld(slot_plane(s), (unsigned)c)) : A(0);
+    }
     dF[s] = A(0);
   }
   if (FUSED) {
@@ -321,62 +370,75 @@ __device__ __forceinline__ void step3_tile(const StepArgs &p, int blk, int G, St
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
       if (d >= p.ndim) break;
+      if (CELL_EARLY && d == p.ndim - 1) cell_load();
       AxisData<A> s;
       load_axis<A, PER>(p, c, q, d, Wc, s);
-      ic_fence();
       constexpr int UNR = sizeof(A) == 8 ? RT_UNROLL_F64 : RT_UNROLL_F32;
       // the plane reads of a slot: cells -1 and +1 and the far upwind cell
       // (-2 for mu_d > 0, else +2).  Those of the PF next slots are issued
       // before the arithmetic of the current one, so that their latency
       // overlaps it.
-      auto reads = [&](int k, S (&r)[3]) {
-        if (slot_m(k) < NA) {
-          const S *Im = slot_plane(k);
-          r[0] = plane_ld(Im, s.idx[1]);
-          r[1] = plane_ld(Im, s.idx[2]);
-          r[2] = plane_ld(Im, slot_rec(k)[rec_n0 + d] > A(0) ? s.idx[0] : s.idx[3]);
+      // (padding slots read the last plane: their zero records make every
+      // term they contribute zero, and the loads stay unconditional so that
+      // the waits for them can be counted precisely)
+      auto reads = [&](int k, S (&r)[4]) {
+        if (RT_UNCOND_LOADS || slot_m(k) < NA) {
+          const S *Im = slot_m(k) < NA ? slot_plane(k) : Iin + (size_t)(NA - 1) * N;
+          const unsigned far = slot_rec(k)[rec_n0 + d] > A(0) ? s.idx[0] : s.idx[3];
+          if constexpr (RT_BUFFER_LOADS) {
+            r[0] = plane_buf_ld(Im, s.idx[1]);
+            r[1] = plane_buf_ld(Im, s.idx[2]);
+            r[2] = plane_buf_ld(Im, far);
+            if constexpr (!IC_REG) r[3] = plane_buf_ld(Im, (unsigned)c);
+          } else {
+            r[0] = plane_ld(Im, s.idx[1]);
+            r[1] = plane_ld(Im, s.idx[2]);
+            r[2] = plane_ld(Im, far);
+            if constexpr (!IC_REG) r[3] = plane_ld(Im, (unsigned)c);
+          }
         } else {
-          r[0] = r[1] = r[2] = S(0);
+          r[0] = r[1] = r[2] = r[3] = S(0);
         }
       };
       constexpr int PF = sizeof(A) == 8 ? RT_PREFETCH_F64 : RT_PREFETCH_F32;
-      S rq[PF][3];
+      S rq[PF][4];
 #pragma unroll
       for (int j = 0; j < PF; ++j)
         if (j < NS) reads(j, rq[j]);
 #pragma unroll UNR
       for (int k = 0; k < NS; ++k) {
-        S r[3];
+        S r[4];
 #pragma unroll
-        for (int t = 0; t < 3; ++t) r[t] = rq[0][t];
+        for (int t = 0; t < 4; ++t) r[t] = rq[0][t];
 #pragma unroll
         for (int j = 0; j + 1 < PF; ++j)
 #pragma unroll
-          for (int t = 0; t < 3; ++t) rq[j][t] = rq[j + 1][t];
+          for (int t = 0; t < 4; ++t) rq[j][t] = rq[j + 1][t];
         if (k + PF < NS) reads(k + PF, rq[PF - 1]);
         const int m = slot_m(k);
+        const int mc = m < NA ? m : NA - 1;
         const A *R = slot_rec(k);  // padding slots: zero records
         const A mud = R[rec_n0 + d];
-        if (m < NA && mud != A(0)) {  // uniform over the wave
+        if (RT_UNCOND_LOADS || (m < NA && mud != A(0))) {  // uniform over the wave
           const A n0 = R[rec_n0], n1 = R[rec_n1], n2 = R[rec_n2];
           const A h2 = R[rec_h0 + d];  // 1 - nu
           // differences of IV = n.W between consecutive stencil cells
           A V[4];
 #pragma unroll
           for (int j = 0; j < 4; ++j) V[j] = n0 * s.dW[j][0] + n1 * s.dW[j][1] + n2 * s.dW[j][2];
-          const A Im1 = plane_value<S, A, PER>(p, r[0], s.idx[1], s.kind[1], 0, d, m, mud);
-          const A Ip1 = plane_value<S, A, PER>(p, r[1], s.idx[2], s.kind[2], 1, d, m, mud);
-          const A ick = icv(k);
+          const A Im1 = plane_value<S, A, PER>(p, r[0], s.idx[1], s.kind[1], 0, d, mc, mud);
+          const A Ip1 = plane_value<S, A, PER>(p, r[1], s.idx[2], s.kind[2], 1, d, mc, mud);
+          const A ick = IC_REG ? Ic[IC_REG ? k : 0] : A(r[3]);
           const A D1 = (ick - Im1) - V[1] * invC;
           const A D2 = (Ip1 - ick) - V[2] * invC;
           A T;
           if (mud > A(0)) {
-            const A Im2 = plane_value<S, A, PER>(p, r[2], s.idx[0], s.kind[0], 0, d, m, mud);
+            const A Im2 = plane_value<S, A, PER>(p, r[2], s.idx[0], s.kind[0], 0, d, mc, mud);
             const A D0 = (Im1 - Im2) - V[0] * invC;
             const A qm = vl_half(D0, D1), q0 = vl_half(D1, D2);
             T = s.cbR * D2 + (s.caL + s.cbL) * D1 + h2 * (s.caR * q0 - s.caL * qm);
           } else {
-            const A Ip2 = plane_value<S, A, PER>(p, r[2], s.idx[3], s.kind[3], 1, d, m, mud);
+            const A Ip2 = plane_value<S, A, PER>(p, r[2], s.idx[3], s.kind[3], 1, d, mc, mud);
             const A D3 = (Ip2 - Ip1) - V[3] * invC;
             const A q0 = vl_half(D1, D2), qp = vl_half(D2, D3);
             T = (s.caR + s.cbR) * D2 + s.cbL * D1 - h2 * (s.caR * qp - s.caL * q0);
@@ -400,18 +462,16 @@ __device__ __forceinline__ void step3_tile(const StepArgs &p, int blk, int G, St
     }
   }
 
-  // the cell's fields, first needed here (loaded after the transport so that
-  // they take no registers there)
-  const double sa = p.sa[c], ss = p.ss[c], rho = p.rho[c], Tn = p.T[c];
-  const double v0 = p.v[c], v1 = p.v[N + c], v2 = p.v[2 * N + c];
+  if (!(FUSED && CELL_EARLY)) cell_load();
+  const double sa = ci.sa, ss = ci.ss, rho = ci.rho, Tn = ci.Tn;
+  const double v0 = ci.v[0], v1 = ci.v[1], v2 = ci.v[2];
 
   // ---------------------------------- Step 3: velocity estimate (per cell)
   double u0 = v0, u1 = v1, u2 = v2;
   if (p.estimate_v) {
     const double h = 0.5 * dt * (sa + ss);
-    const double E = p.mom_in[c];
-    const double F0 = p.mom_in[N + c], F1 = p.mom_in[2 * N + c], F2 = p.mom_in[3 * N + c];
-    const double P0 = p.mom_in[4 * N + c], P1 = p.mom_in[5 * N + c], P2 = p.mom_in[6 * N + c];
+    const double E = ci.E, F0 = ci.F[0], F1 = ci.F[1], F2 = ci.F[2];
+    const double P0 = ci.P[0], P1 = ci.P[1], P2 = ci.P[2];
     const double base = rho + h * C * rho;
     const double hPC = h * P * iC;
     u0 = (rho * v0 + h * (C * rho * v0 + P * F0)) * fast_rcp(base + hPC * (E + P0));
@@ -432,7 +492,6 @@ __device__ __forceinline__ void step3_tile(const StepArgs &p, int blk, int G, St
   A sm[kNsum];
 #pragma unroll
   for (int r = 0; r < kNsum; ++r) sm[r] = A(0);
-  ic_fence();
 #pragma unroll
   for (int k = 0; k < NS; ++k) {
     pk[k] = A(0);
@@ -449,7 +508,7 @@ __device__ __forceinline__ void step3_tile(const StepArgs &p, int blk, int G, St
     const A gg = Auu + t * t;
     const A b = B0 + A(2) * dss * t - dssC * t * t;
     const A cm = A(-3) * dss * t;
-    const A ick = icv(k);
+    const A ick = IC_REG ? Ic[IC_REG ? k : 0] : A(plane_ld(slot_plane(k), (unsigned)c));
     const A r4 = ick + g4 * dF[k];
     const A pm = r4 * invD + g5 * dF[k];
     pk[k] = pm;
@@ -484,55 +543,81 @@ __device__ __forceinline__ void step3_tile(const StepArgs &p, int blk, int G, St
     Sa[r] = double(sm[r]);
     Sb[r] = double(sm[kChunk + r]);
   }
-  waves_reduce<kChunk, false, Step3Smem<S>::R>(Sa, sbuf, stot, g, G, lane);
-  waves_reduce<kChunk, false, Step3Smem<S>::R>(Sb, sbuf, stot, g, G, lane);
+  waves_reduce<kChunk, false, kChunk>(Sa, sbuf, stot, g, G, lane);
+  waves_reduce<kChunk, false, kChunk>(Sb, sbuf, stot, g, G, lane);
   // Sa = sums 0..10, Sb = sums 11..21
 
-  // --------------------------------------------- solve (FP64, wave 0)
+  // --------------------------------------------- solve (FP64)
+  // Every wave holds the reduced sums of its 64 cells, so every wave can
+  // solve them (RT_SOLVE_ALL, no barrier and no idle waves), or wave 0
+  // solves and passes the solution on through LDS.
   const double kap = dt * sa * iC;
   const double cv = rho * p.cvfac;
-  if (g == 0) {
+  double X = 0.0, kQ = 0.0, s1 = 0.0, s2 = 0.0, T = 0.0, newton_it = 0.0;
+  if (RT_SOLVE_ALL || g == 0) {
     const double qden = 1.0 + kap * Sa[8];
     const double iqden = fast_rcp(qden);
     const double q0 = Sa[6] * iqden, q1 = Sa[7] * iqden;
     const double j0 = Sa[0] - kap * Sa[2] * q0, j1 = Sa[1] - kap * Sa[2] * q1;
     const double k0 = Sa[3] - kap * Sa[5] * q0, k1 = Sa[4] - kap * Sa[5] * q1;
-    const double beta = P * C * (1.0 - uu / (C * C)) * sa * dt;
+    const double beta = P * C * (1.0 - uu * iC * iC) * sa * dt;
     const double g8 = 8.0 * kPi * P * sa * dt;
     const double h0 = -g8 * (k0 - q0 * iC) + kFourPi * beta * j0;
     const double h1q = (-g8 * (k1 - q1 * iC) - kFourPi * beta * (1.0 - j1)) * (1.0 / kFourPi);
-    double T = Tn;
+    double Tt = Tn;
     int it;
     bool conv = false;
     for (it = 1; it <= p.maxit; ++it) {
-      const double T3 = T * T * T;
-      const double f = cv * (T - Tn) - h0 - h1q * T3 * T;
+      const double T3 = Tt * Tt * Tt;
+      const double f = cv * (Tt - Tn) - h0 - h1q * T3 * Tt;
       const double dT = f * fast_rcp(cv - 4.0 * h1q * T3);
-      T -= dT;
-      if (fabs(dT) <= p.rtol * fabs(T)) {
+      Tt -= dT;
+      if (fabs(dT) <= p.rtol * fabs(Tt)) {
         conv = true;
         break;
       }
     }
-    if (act && (!conv || !(T > 0.0) || !isfinite(T))) atomicOr(p.status, 1);
-    const double X = T * T * T * T * (1.0 / kFourPi);
+    if (g == 0 && act && (!conv || !(Tt > 0.0) || !isfinite(Tt))) atomicOr(p.status, 1);
+    X = Tt * Tt * Tt * Tt * (1.0 / kFourPi);
     const double Q = q0 + q1 * X;
     const double Sbr = Sa[9] + X * Sb[4] - kap * Q * Sb[5];
     const double Sr5 = Sa[10] + X * Sb[6] - kap * Q * Sb[7];
     const double a11 = 1.0 + Sb[0], a12 = Sb[1], a21 = Sb[2], a22 = 1.0 + Sb[3];
     const double det = a11 * a22 - a12 * a21;
-    ssol[0 * 64 + lane] = X;
-    ssol[1 * 64 + lane] = kap * Q;
     const double idet = fast_rcp(det);
-    ssol[2 * 64 + lane] = (Sbr * a22 - a12 * Sr5) * idet;
-    ssol[3 * 64 + lane] = (a11 * Sr5 - a21 * Sbr) * idet;
-    ssol[4 * 64 + lane] = T;
-    ssol[5 * 64 + lane] = double(it);
+    kQ = kap * Q;
+    s1 = (Sbr * a22 - a12 * Sr5) * idet;
+    s2 = (a11 * Sr5 - a21 * Sbr) * idet;
+    T = Tt;
+    newton_it = double(it);
   }
-  __syncthreads();
-  const double X = ssol[lane], kQ = ssol[64 + lane], s1 = ssol[128 + lane],
-               s2 = ssol[192 + lane], T = ssol[256 + lane];
-  const double newton_it = ssol[320 + lane];
+  if constexpr (!RT_SOLVE_ALL) {
+    if (g == 0) {
+      ssol[0 * 64 + lane] = X;
+      ssol[1 * 64 + lane] = kQ;
+      ssol[2 * 64 + lane] = s1;
+      ssol[3 * 64 + lane] = s2;
+      ssol[4 * 64 + lane] = T;
+      ssol[5 * 64 + lane] = newton_it;
+    }
+    __syncthreads();
+    X = ssol[lane];
+    kQ = ssol[64 + lane];
+    s1 = ssol[128 + lane];
+    s2 = ssol[192 + lane];
+    T = ssol[256 + lane];
+    newton_it = ssol[320 + lane];
+  }
+
+  // the sums of the earlier steps of the call that this wave's outputs add
+  // to, loaded here so that their latency overlaps phase C
+  double accE = 0.0, accM[3] = {0.0, 0.0, 0.0};
+  if (p.accumulate) {
+    if (p.dEgas && 14 % G == g) accE = p.dEgas[c];
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+      if (p.dMom && (15 + k) % G == g) accM[k] = p.dMom[(size_t)k * N + c];
+  }
 
   // --------------------------------------- phase C: new intensities
   const A AX = A(X), AkQ = A(kQ), As1 = A(s1), As2 = A(s2);
@@ -559,7 +644,7 @@ __device__ __forceinline__ void step3_tile(const StepArgs &p, int blk, int G, St
     for (int r = 0; r < 10; ++r) mo[r] += Rgd[(unsigned)slot_off(k) * kRec + rec_w + r] * In;
     mo[10] = In < mo[10] ? In : mo[10];
   }
-  waves_reduce<kChunk, true, Step3Smem<S>::R>(mo, sbuf, stot, g, G, lane);
+  waves_reduce<kChunk, true, kChunk>(mo, sbuf, stot, g, G, lane);
 #pragma unroll
   for (int r = 0; r < 10; ++r) mo[r] *= kFourPi;
 
@@ -610,12 +695,12 @@ __device__ __forceinline__ void step3_tile(const StepArgs &p, int blk, int G, St
         dst = p.T;
       } else if (f == 14) {
         if (!p.dEgas) continue;
-        val = (p.accumulate ? p.dEgas[c] : 0.0) + deg;
+        val = accE + deg;
         dst = p.dEgas;
       } else if (f < 18) {
         if (!p.dMom) continue;
         const int k = f - 15;
-        val = (p.accumulate ? p.dMom[(size_t)k * N + c] : 0.0) + (k == 0 ? dm0 : k == 1 ? dm1 : dm2);
+        val = accM[k] + (k == 0 ? dm0 : k == 1 ? dm1 : dm2);
         dst = p.dMom + (size_t)k * N;
       } else if (f == 18) {
         if (!p.oE) continue;
@@ -688,11 +773,11 @@ template <typename S, typename A, int KA, int NG, bool PER, bool FUSED>
 __global__ __launch_bounds__(64 * kMaxWaves, sizeof(S) == 8 ? RT_STEP3_WAVES_F64
                                                             : RT_STEP3_WAVES_F32) void
 k_step3(StepArgs p) {
-  __shared__ Step3Smem<S> sm_;
+  extern __shared__ double lds_[];
   constexpr int ORD = sizeof(S) == 8 ? RT_BLOCK_ORDER_F64 : RT_BLOCK_ORDER_F32;
   const int b = (int)blockIdx.x, nb = (int)gridDim.x;
   const int blk = ORD == 2 ? slab_block(b, nb, p.n) : ORD == 1 ? xcd_block(b, nb) : b;
-  step3_tile<S, A, KA, NG, PER, FUSED>(p, blk, blockDim.x >> 6, sm_);
+  step3_tile<S, A, KA, NG, PER, FUSED>(p, blk, blockDim.x >> 6, lds_);
 }
 
 // A whole solve per workgroup: job blockIdx.x advances its grid through
@@ -704,7 +789,7 @@ k_step3(StepArgs p) {
 template <typename S, typename A, int KA, int NG, bool PER>
 __global__ __launch_bounds__(64 * kMaxWaves) void k_step3_packed(
     const PackedJob *__restrict__ jobs) {
-  __shared__ Step3Smem<S> sm_;
+  extern __shared__ double lds_[];
   __shared__ double red[kNtot * kVWaves];
   const PackedJob &J = jobs[blockIdx.x];
   StepArgs p = J.a;
@@ -723,7 +808,7 @@ __global__ __launch_bounds__(64 * kMaxWaves) void k_step3_packed(
     p.oF = last ? oF : nullptr;
     p.oP = last ? oP : nullptr;
     for (int t = 0; t < ntiles; ++t)
-      step3_tile<S, A, KA, NG, PER, true>(p, t, kMaxWaves, sm_);
+      step3_tile<S, A, KA, NG, PER, true>(p, t, kMaxWaves, lds_);
     __threadfence();
     __syncthreads();
   }
