@@ -56,7 +56,9 @@ typedef enum rt_status {
                           converge, or gave a non-positive/non-finite T     */
   RT_EBADQUAD = -6,    /* weights do not sum to 1 or |n| != 1               */
   RT_ESTATE = -7,      /* call order violated (e.g. no intensity bound)     */
-  RT_EUNSUPPORTED = -8 /* valid request the library does not support        */
+  RT_EUNSUPPORTED = -8, /* valid request the library does not support       */
+  RT_ETOOBIG = -9      /* (rt_step_static) the problem's scratch exceeds
+                          RT_STATIC_SCRATCH_BYTES                           */
 } rt_status;
 
 enum { RT_BC_PERIODIC = 0, RT_BC_FIXED = 1, RT_BC_COPY = 2, RT_BC_VACUUM = 3 };
@@ -242,6 +244,33 @@ int rt_source_implicit(rt_ctx *ctx, double dt, const rt_fields *f, const void *d
  * are those after the last step. */
 int rt_step(rt_ctx *ctx, double dt, int nsteps, const rt_fields *f, rt_out *out,
             void *stream);
+
+/* Library scratch per GPU of rt_step_static, in bytes (64 MiB): a device
+ * array that each GPU the library runs on holds until the process ends. */
+#define RT_STATIC_SCRATCH_BYTES (64ull << 20)
+
+/* For callers that cannot allocate device memory -- code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc: the
+ * sequence rt_create, rt_bind_intensity(I_a, I_b), rt_step(nsteps),
+ * rt_destroy as one call that allocates nothing.  The library scratch the
+ * context would allocate (angle tables, two moment fields, the interface
+ * table, partial totals) is carved from a file-scope device array of
+ * RT_STATIC_SCRATCH_BYTES per GPU instead, so a problem fits when it needs
+ * about 282 bytes per cell plus 300 per direction (64^3 cells does not; 60^3
+ * does); larger ones return RT_ETOOBIG before any device work.  Arguments,
+ * layouts and results are those of the calls it stands for: I_a holds the
+ * current intensities on entry; after the call the newest are in I_a when
+ * nsteps is even and in I_b when it is odd.  Fixed faces take zero inflow
+ * (the call has no ghost tables).  status is a caller-owned device int that
+ * a step ORs with 1 when the temperature iteration fails (what rt_sync_status
+ * reports for a context); the caller clears it.  Every call on a GPU shares
+ * that GPU's array, whose contents the last call leaves behind: calls that
+ * overlap on one GPU (other threads, or streams that run concurrently) race,
+ * and are the caller's to order.  Errors as rt_create and rt_step, plus
+ * RT_ETOOBIG. */
+int rt_step_static(const rt_grid *g, const rt_angles *a, const rt_params *p, void *I_a,
+                   void *I_b, double dt, int nsteps, const rt_fields *f, rt_out *out,
+                   int *status, void *stream);
 
 /* Fills the intensity buffer I ([nang][ncell], storage type) with the
  * equilibrium intensity T^4/(4 pi) of the device temperatures T ([ncell]

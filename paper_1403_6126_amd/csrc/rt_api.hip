@@ -5,6 +5,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -77,6 +78,12 @@ __global__ __launch_bounds__(kBlock) void k_faces(StepArgs p, double *faces, dou
   }
   const double J = mom[c] * (1.0 / kFourPi);
   for (int k = 0; k < 3; ++k) mom[(size_t)(10 + k) * N + c] = p.ivfac * p.v[(size_t)k * N + c] * J;
+}
+
+// Sets one int in device memory (status words; a kernel, not a memset, so
+// that a captured graph replays it correctly).
+__global__ void k_set_int(int *p, int v) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *p = v;
 }
 
 __global__ __launch_bounds__(kVLanes) void k_totals(const double *partials, int nblocks,
@@ -442,10 +449,11 @@ int ctx_attach_scratch(rt_ctx *c, char *base, hipStream_t s) {
       hip_ok(hipMemcpyAsync(c->d_wf, c->h_wf.data(), sizeof(float) * N, hipMemcpyHostToDevice,
                             s)) &&
       hip_ok(hipMemcpyAsync(c->d_ghost, c->h_ghost.data(), sizeof(double) * 6 * N,
-                            hipMemcpyHostToDevice, s)) &&
-
-      hip_ok(hipMemsetAsync(c->status, 0, sizeof(int), s));
-  return ok ? RT_OK : RT_EDEVICE;
+                            hipMemcpyHostToDevice, s));
+  if (!ok) return RT_EDEVICE;
+  clear_stale_error();
+  hipLaunchKernelGGL(k_set_int, dim3(1), dim3(64), 0, s, c->status, 0);
+  return hip_ok(hipGetLastError()) ? RT_OK : RT_EDEVICE;
 }
 
 int ctx_moments(rt_ctx *c, hipStream_t s) {
@@ -508,9 +516,85 @@ int ctx_init_equilibrium(rt_ctx *c, const double *T, void *I, hipStream_t s) {
 
 }  // namespace rtk
 
+// ------------------------------------------------------ static scratch
+// The library scratch of rt_step_static: one array per GPU (each device that
+// runs the library holds its own copy until the process ends).  Host code
+// reaches it only through the device address that hipGetSymbolAddress gives
+// for the current device, once per device, kept in static_ptr[]; the array's
+// name is a host-side stand-in, not a device address.
+static __device__ __align__(256) char scratch[RT_STATIC_SCRATCH_BYTES];
+
+namespace {
+constexpr int kStaticDevices = 16;
+std::mutex static_mu;
+char *static_ptr[kStaticDevices];
+// Host contexts of rt_step_static, one per device, with their host tables
+// reserved for RT_MAX_ANGLES directions when the library loads, so that the
+// calls themselves allocate nothing (the tables are refilled in place).
+rt_ctx *static_ctx[kStaticDevices];
+
+__attribute__((constructor)) void static_ctx_init() {
+  for (int d = 0; d < kStaticDevices; ++d) {
+    rt_ctx *c = new (std::nothrow) rt_ctx();
+    if (!c) continue;
+    const size_t N = RT_MAX_ANGLES;
+    c->h_mu.reserve(3 * N);
+    c->h_w.reserve(N);
+    c->h_ghost.reserve(6 * N);
+    c->h_muf.reserve(3 * N);
+    c->h_wf.reserve(N);
+    static_ctx[d] = c;
+  }
+}
+}  // namespace
+
 using namespace rtk;
 
 extern "C" {
+
+int rt_step_static(const rt_grid *g, const rt_angles *an, const rt_params *p, void *Ia, void *Ib,
+                   double dt, int nsteps, const rt_fields *f, rt_out *o, int *status,
+                   void *stream) {
+  if (!g || !an || !p || !Ia || !Ib || Ia == Ib || !fields_ok(f) || !status || nsteps < 0)
+    return RT_EINVAL;
+  int dev = -1;
+  if (!hip_ok(hipGetDevice(&dev)) || dev < 0 || dev >= kStaticDevices) return RT_EDEVICE;
+  char *base = nullptr;
+  {
+    std::lock_guard<std::mutex> lk(static_mu);
+    if (!static_ptr[dev]) {
+      void *ptr = nullptr;
+      if (!hip_ok(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch))) || !ptr) {
+        clear_stale_error();
+        return RT_EDEVICE;
+      }
+      static_ptr[dev] = static_cast<char *>(ptr);
+    }
+    base = static_ptr[dev];
+  }
+  rt_ctx *c = static_ctx[dev];
+  if (!c) return RT_ENOMEM;
+  c->owns_device = false;
+  c->profile = false;
+  for (auto &t : c->d_gface) t = nullptr;
+  int st = ctx_init_host(g, an, p, c);
+  if (st != RT_OK) return st;
+  if (ctx_scratch_bytes(c) > RT_STATIC_SCRATCH_BYTES) return RT_ETOOBIG;
+  if ((c->p.flags & RT_GAS_FEEDBACK) && !c->shape.waves) return RT_EUNSUPPORTED;
+  st = ctx_check_dt(c, dt);
+  if (st != RT_OK) return st;
+  hipStream_t s = (hipStream_t)stream;
+  st = ctx_attach_scratch(c, base, s);
+  if (st != RT_OK) return st;
+  c->status = status;  // the caller's flag
+  c->I[0] = Ia;
+  c->I[1] = Ib;
+  c->cur = 0;
+  c->mom_cur = 0;
+  c->mom_valid = false;
+  return ctx_step(c, dt, nsteps, f, o, s);
+}
+
 
 const char *rt_strerror(int st) {
   switch (st) {
@@ -524,6 +608,7 @@ const char *rt_strerror(int st) {
     case RT_EBADQUAD: return "invalid angle set (weights or direction norms)";
     case RT_ESTATE: return "call order violated (no intensity bound?)";
     case RT_EUNSUPPORTED: return "unsupported request";
+    case RT_ETOOBIG: return "problem scratch exceeds the static scratch array";
     default: return "unknown status";
   }
 }

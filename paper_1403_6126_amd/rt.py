@@ -20,7 +20,8 @@ LIB_PATH = os.path.join(HERE, "librt.so")
 
 RT_PENDING = 1
 RT_OK, RT_EINVAL, RT_ENOMEM, RT_EDEVICE, RT_ECFL, RT_ENOCONV, RT_EBADQUAD, RT_ESTATE, \
-    RT_EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6, -7, -8
+    RT_EUNSUPPORTED, RT_ETOOBIG = 0, -1, -2, -3, -4, -5, -6, -7, -8, -9
+RT_STATIC_SCRATCH_BYTES = 64 << 20
 RT_BC_PERIODIC, RT_BC_FIXED, RT_BC_COPY, RT_BC_VACUUM = 0, 1, 2, 3
 RT_FP64, RT_FP32_MIXED = 0, 1
 RT_QUAD_GAUSS_LEGENDRE, RT_QUAD_LEVEL_SYMMETRIC = 0, 1
@@ -120,6 +121,10 @@ SIGNATURES = [
                                       ct.c_void_p, ct.POINTER(rt_out), ct.c_void_p]),
     ("rt_step", ct.c_int, [ct.c_void_p, ct.c_double, ct.c_int, ct.POINTER(rt_fields),
                            ct.POINTER(rt_out), ct.c_void_p]),
+    ("rt_step_static", ct.c_int, [ct.POINTER(rt_grid), ct.POINTER(rt_angles),
+                                  ct.POINTER(rt_params), ct.c_void_p, ct.c_void_p, ct.c_double,
+                                  ct.c_int, ct.POINTER(rt_fields), ct.POINTER(rt_out),
+                                  ct.c_void_p, ct.c_void_p]),
     ("rt_equilibrium_intensity", ct.c_int, [ct.c_void_p, ct.c_void_p, ct.c_void_p,
                                             ct.c_void_p]),
     ("rt_sync_status", ct.c_int, [ct.c_void_p]),
@@ -279,6 +284,18 @@ def rt_step(ctx: int, dt: float, nsteps: int, fields: rt_fields, out: rt_out | N
     _check(lib().rt_step(ct.c_void_p(ctx), dt, nsteps, ct.byref(fields),
                          ct.byref(out) if out is not None else None, ct.c_void_p(stream)),
            "rt_step")
+
+
+def rt_step_static(grid: rt_grid, mu: np.ndarray, w: np.ndarray, params: rt_params, I_a, I_b,
+                   dt: float, nsteps: int, fields: rt_fields, out: rt_out | None, status,
+                   stream=0) -> None:
+    mu = np.ascontiguousarray(mu, dtype=np.float64)
+    w = np.ascontiguousarray(w, dtype=np.float64)
+    ang = rt_angles(len(w), _dptr(mu), _dptr(w))
+    _check(lib().rt_step_static(ct.byref(grid), ct.byref(ang), ct.byref(params), _vp(I_a),
+                                _vp(I_b), dt, nsteps, ct.byref(fields),
+                                ct.byref(out) if out is not None else None, _vp(status),
+                                ct.c_void_p(stream)), "rt_step_static")
 
 
 def rt_equilibrium_intensity(ctx: int, T, I, stream=0) -> None:
