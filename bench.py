@@ -9,9 +9,12 @@ and quadrature for every cell and angle, plus the small reduction of the
 domain totals.  Inputs are resident in device memory before timing starts.
 
 Prints one JSON line (rank 0): the FP64 throughput in cell-angle updates/s,
-the roofline of the fused kernel (algorithmic bytes per launch over the mean
-launch time from HIP events recorded around each launch on its stream), the
-FP32-mixed throughput, and the CPU oracle's rate on a bounded sample.
+the HBM roofline of the fused kernel (algorithmic bytes per launch over the
+mean launch time from HIP events recorded around each launch on its stream)
+and its VALU-issue roofline (algorithmic operations over the same time), the
+FP32-mixed throughput on the same box and on the 256^3 shadow and
+512x512x256 diffusion boxes, the serving trace against the plain path, and
+the CPU oracle's steps-only rate on the host.
 """
 from __future__ import annotations
 
@@ -27,6 +30,25 @@ sys.path.insert(0, ROOT)
 METRIC = "cell-angle updates/s, FP64 vs FP32-mixed; p50/p99 latency of served solves"
 HBM_PEAK_GBS = 8000.0
 FIELD_BYTES_PER_CELL = 232  # 14 FP64 per-cell reads + 15 FP64 per-cell writes
+# VALU issue peak of one MI355X: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz lane
+# operations per second (one FP64, or unpacked FP32, operation per lane and
+# cycle; an FMA counts as one operation).
+VALU_ISSUE_PEAK = 256 * 4 * 16 * 2.4e9
+# Algorithmic VALU operations of one 3D cell-angle update, counted from the
+# method with every interface value formed once (shared by its two cells)
+# and the per-cell work amortised over the angles:
+#   transport (Section 4.2), per angle: IV = n.W (3), I~ = I - IV/C (1); per
+#     axis: the two differences (2), the two van Leer slopes (5 each: product,
+#     sum, reciprocal, quotient, select), the upwind I~ and IV face values
+#     (3), the alpha blend (3), the flux C x + IV* (1), the increment (2):
+#     4 + 3 x 21 = 67;
+#   source (Sections 4.3-4.5), per angle: n.u (3), D and the scattering
+#     diagonal (2), their reciprocals (4), e, g, b, c (5), the routing (2),
+#     the 22 sums of the reduced systems with their 7 shared products (29),
+#     the new intensity (6), the 10 moments (10): 61.
+ALG_OPS_PER_CELL_ANGLE_3D = 128
+STEP_SOURCES = ("rt_step3.hpp", "rt_common.hpp", "rt_internal.hpp", "rt_kernels.inc",
+                "rt_kernels_f64.hip", "rt_kernels_f32.hip")
 
 
 def algorithmic_bytes_per_cell(nang: int, sbytes: int) -> int:
@@ -34,18 +56,65 @@ def algorithmic_bytes_per_cell(nang: int, sbytes: int) -> int:
     return 2 * sbytes * nang + FIELD_BYTES_PER_CELL
 
 
-def load_traffic(kernel: str, workload: str):
-    """HBM bytes per launch measured with rocprofv3 counters, if a summary for
-    this kernel and workload is committed under profiles/."""
-    path = os.path.join(ROOT, "profiles", f"traffic_{kernel}_{workload}.json")
+def kernel_source_sha() -> str:
+    """Digest of the fused step kernel's sources and build flags: counters
+    taken on another kernel do not describe this one."""
+    import hashlib
+
+    from paper_1403_6126_amd import build as B
+    h = hashlib.sha256()
+    for name in STEP_SOURCES:
+        with open(os.path.join(B.CSRC, name), "rb") as f:
+            h.update(f.read())
+    h.update(" ".join(B.HIPCC_FLAGS).encode())
+    h.update(json.dumps(B.EXTRA_FLAGS, sort_keys=True).encode())
+    return h.hexdigest()[:16]
+
+
+def load_traffic(tag: str, workload: str):
+    """HBM bytes per launch of the fused kernel from rocprofv3 FETCH_SIZE and
+    WRITE_SIZE counters, as committed under profiles/ (file name returned as
+    the source), or None when no summary exists or it was taken on other
+    kernel sources than the ones built now."""
+    rel = os.path.join("profiles", f"traffic_{tag}_{workload}.json")
+    path = os.path.join(ROOT, rel)
     if not os.path.exists(path):
-        return None
+        return None, None
     try:
         with open(path) as f:
             d = json.load(f)
-        return d.get("bytes_per_launch")
     except Exception:
-        return None
+        return None, None
+    if d.get("kernel_source_sha") != kernel_source_sha():
+        return None, rel + " (taken on other kernel sources)"
+    return d.get("bytes_per_launch"), rel
+
+
+def kernel_name(info, storage_bytes: int) -> str:
+    """The fused kernel instance of a context's launch shape."""
+    t = "double" if storage_bytes == 8 else "float"
+    waves = max(1, info["block_threads"] // 64)
+    ng = -(-info["nang"] // 10)
+    groups = -(-ng // waves)
+    return f"rtk::k_step3<{t}, {t}, 10, {groups}, true, true>"
+
+
+def rooflines(r, tag: str, wname: str):
+    """HBM roofline (algorithmic bytes over the kernel time against the 8 TB/s
+    peak, with the counters' traffic) and VALU-issue roofline (algorithmic
+    operations over the kernel time against the issue peak) of one run."""
+    traffic, source = load_traffic(tag, wname)
+    kname = kernel_name(r, r["storage_bytes"])
+    upd_per_s = r["updates_per_launch"] / (r["kernel_ms"] * 1e-3)
+    ops = ALG_OPS_PER_CELL_ANGLE_3D * upd_per_s
+    hbm = {"bound": "hbm", "achieved": r["achieved_gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+           "frac": r["achieved_gbs"] / HBM_PEAK_GBS, "traffic": traffic,
+           "traffic_source": source, "kernel": kname, "kernel_ms": r["kernel_ms"],
+           "bytes_per_launch": r["bytes_per_launch"]}
+    alu = {"bound": "alu", "achieved": ops / 1e12, "peak": VALU_ISSUE_PEAK / 1e12,
+           "unit": "Tops/s (VALU issue)", "frac": ops / VALU_ISSUE_PEAK,
+           "ops_per_cell_angle": ALG_OPS_PER_CELL_ANGLE_3D, "kernel": kname}
+    return hbm, alu
 
 
 def run_gpu(wl, precision: str, steps: int, warmup: int, second_order: bool = False):
@@ -56,10 +125,17 @@ def run_gpu(wl, precision: str, steps: int, warmup: int, second_order: bool = Fa
     from paper_1403_6126_amd.solver import Solver, quadrature_for
 
     mu, w = quadrature_for(wl.quad)
-    T = torch.as_tensor(wl.T).cuda()
-    I0 = W.equilibrium_intensity(T, len(w), xp=torch)  # (nang, ncell), expanded view
+    if "E0" in wl.meta:   # I = (E + 3 n.F)/(4 pi), built on the device
+        E = torch.as_tensor(wl.meta["E0"], device="cuda")
+        F = torch.as_tensor(wl.meta["F0"], device="cuda")
+        I0 = W.moment_intensity(torch.as_tensor(mu, device="cuda"), E, F, xp=torch)
+        del E, F
+    else:                 # I = T^4/(4 pi), an expanded view
+        T = torch.as_tensor(wl.T).cuda()
+        I0 = W.equilibrium_intensity(T, len(w), xp=torch)
     s = Solver(wl, precision=precision, mu=mu, w=w, I0=I0, second_order=second_order)
     del I0
+    torch.cuda.empty_cache()
     info = rt.rt_get_info(s.ctx)
     stream = torch.cuda.current_stream().cuda_stream
     if warmup:
@@ -86,35 +162,82 @@ def run_gpu(wl, precision: str, steps: int, warmup: int, second_order: bool = Fa
     return dict(value=upd / wall, ms_per_step=wall / steps * 1e3, kernel_ms=kavg * 1e3,
                 launches=nl, bytes_per_launch=bpl, achieved_gbs=bpl / kavg / 1e9,
                 nang=info.nang, storage_bytes=info.storage_bytes, totals=totals,
-                grid_blocks=info.grid_blocks, block_threads=info.block_threads)
+                grid_blocks=info.grid_blocks, block_threads=info.block_threads,
+                updates_per_launch=wl.ncell * info.nang)
 
 
-def cpu_baseline(wl, budget_s: float = 12.0, batch: int = 65536, seed: int = 0,
-                 threads: int = 0):
-    """The CPU oracle (as it stands) on a bounded sample of the same workload:
-    one step evaluated on batches of random cells of the 128^3 box until the
-    time budget is spent, on all host threads or on `threads` of them."""
-    import numpy as np
+def _host_cpu():
+    """Thread count and processor model of the host the oracle runs on."""
+    model = ""
+    try:
+        import subprocess
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        for line in out.splitlines():
+            if line.startswith("Model name:"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except Exception:
+        pass
+    return os.cpu_count(), model
 
+
+def cpu_baseline(threads: int = 0):
+    """The CPU oracle (as it stands, plain FP64 C) timed on the host: steps
+    only, the workload already in memory.  One full step of the 128^3 S8 box
+    (the GPU line's workload) on all threads, and the 512-cell GL16 slab
+    (100 steps) on one thread and on all threads."""
     import oracle
+    import workloads as W
 
+    nproc, model = _host_cpu()
     if threads > 0:
         oracle.set_threads(threads)
-    prob = oracle.Problem(wl)
-    I = wl.init(prob.mu)
-    rng = np.random.default_rng(seed)
-    done = 0
-    t0 = time.perf_counter()
-    while time.perf_counter() - t0 < budget_s:
-        cells = np.sort(rng.choice(wl.ncell, batch, replace=False))
-        oracle.step_cells(prob, I, wl.T, cells)
-        done += len(cells)
-    el = time.perf_counter() - t0
-    return dict(value=done * prob.nang / el, unit="cell-angle updates/s", cores=oracle.threads(),
-                kind="oracle",
-                sample=f"one step at {done} randomly sampled cells of the 128^3 S8 FP64 box "
-                       f"(batches of {batch}; each batch also takes the moments of all cells), "
-                       f"{el:.1f} s")
+    nthr = oracle.threads()
+
+    def rate(wl, nsteps):
+        st = oracle.State(oracle.Problem(wl))
+        t0 = time.perf_counter()
+        st.step(nsteps=nsteps)
+        el = time.perf_counter() - t0
+        return wl.ncell * st.prob.nang * nsteps / el, el
+
+    slab = W.config1()
+    oracle.set_threads(1)
+    r1, t1 = rate(slab, 100)
+    oracle.set_threads(nthr)
+    rn, tn = rate(slab, 100)
+    box = W.config2()
+    rb, tb = rate(box, 1)
+    return dict(value=rb, unit="cell-angle updates/s", cores=nthr, kind="oracle",
+                sample=f"one full step of the 128^3 S8 FP64 box on {nthr} threads, steps only "
+                       f"({tb:.1f} s)",
+                per_core=rb / nthr, nproc=nproc, cpu_model=model,
+                slab_512_gl16_100_steps={"threads_1": r1, f"threads_{nthr}": rn,
+                                         "seconds": [t1, tn]})
+
+
+def configs_leg(steps: int = 5, warmup: int = 2):
+    """The FP32-mixed fused step on the other full-size workloads: the 256^3
+    shadow box (fixed faces, beam, clump) and the 512x512x256 advective
+    diffusion box.  Kernel time from the same HIP events as the main line."""
+    import torch
+
+    import workloads as W
+    out = {}
+    for name, make in (("shadow3d_256cube_S8_fixed", lambda: W.config3(nper=256)),
+                       ("diffusion3d_512x512x256_S8", lambda: W.config5())):
+        print(f"bench: {name} mixed warmup={warmup} steps={steps}", file=sys.stderr, flush=True)
+        wl = make()
+        r = run_gpu(wl, "mixed", steps, warmup)
+        del wl
+        torch.cuda.empty_cache()
+        hbm, alu = rooflines(r, "k_step3_mixed", name)
+        out[name] = dict(value=r["value"], ms_per_step=r["ms_per_step"], kernel_ms=r["kernel_ms"],
+                         cells=r["updates_per_launch"] // r["nang"], angles=r["nang"],
+                         roofline=hbm, compute_roofline=alu)
+        print(f"bench: {name} {r['value']:.4g} cell-angle/s, kernel {r['kernel_ms']:.3f} ms",
+              file=sys.stderr, flush=True)
+    return out
 
 
 SERVE_DEFAULTS = dict(pool_bytes=96 << 30, max_active=1024, packed_cells=4096,
@@ -178,7 +301,13 @@ def main():
     ap.add_argument("--nper", type=int, default=128, help="cells per axis (128 = full workload)")
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-budget", type=float, default=12.0)
+    ap.add_argument("--no-configs", action="store_true",
+                    help="skip the FP32-mixed timing of the 256^3 shadow and 512x512x256 "
+                         "diffusion boxes")
+    ap.add_argument("--only-configs", action="store_true",
+                    help="profiling: run the shadow and diffusion timing alone")
+    ap.add_argument("--config-steps", type=int, default=5,
+                    help="timed steps of the shadow and diffusion boxes")
     ap.add_argument("--cpu-threads", type=int, default=0,
                     help="threads of the CPU-baseline leg (0: all host threads)")
     ap.add_argument("--only-cpu", action="store_true",
@@ -206,9 +335,7 @@ def main():
               "not code)", file=sys.stderr)
         sys.exit(2)
     if args.only_cpu:
-        import workloads as W
-        print(json.dumps(cpu_baseline(W.config2(nper=args.nper), args.cpu_budget,
-                                      threads=args.cpu_threads)), flush=True)
+        print(json.dumps(cpu_baseline(threads=args.cpu_threads)), flush=True)
         return
 
     import torch
@@ -236,6 +363,9 @@ def main():
         print(json.dumps({"copy_probe_bytes_each_way": 8 * n, "launches": args.steps,
                           "ms_per_copy": ms, "read_plus_write_gbs": 2 * 8 * n / ms / 1e6}))
         return
+    if args.only_configs:
+        print(json.dumps(configs_leg(steps=args.config_steps)), flush=True)
+        return
     if args.only_serve:
         print(json.dumps(serving(args.serve_requests, args.serve_load, args.serve_warm)),
               flush=True)
@@ -261,22 +391,22 @@ def main():
         rmx = run_gpu(wl, "mixed", args.steps, args.warmup)
         print(f"bench: mixed {rmx['value']:.4g} cell-angle/s, kernel {rmx['kernel_ms']:.3f} ms",
               file=sys.stderr, flush=True)
+        hbm, alu = rooflines(rmx, "k_step3_mixed", wname)
         mixed = dict(value=rmx["value"], ms_per_step=rmx["ms_per_step"], dtype="f32 (I), f64 (T)",
-                     roofline=dict(bound="hbm", achieved=rmx["achieved_gbs"], peak=HBM_PEAK_GBS,
-                                   unit="GB/s", frac=rmx["achieved_gbs"] / HBM_PEAK_GBS,
-                                   traffic=load_traffic("k_step3_mixed", wname),
-                                   kernel="rtk::k_step3<float, float, 10, 1, true, true>",
-                                   kernel_ms=rmx["kernel_ms"],
-                                   bytes_per_launch=rmx["bytes_per_launch"]))
+                     roofline=hbm, compute_roofline=alu)
+    others = None
+    if not args.no_configs:
+        torch.cuda.empty_cache()
+        others = configs_leg(steps=args.config_steps)
     srv = None
     if args.serve_requests > 0:
-        import torch
         torch.cuda.empty_cache()
         srv = serving(args.serve_requests, args.serve_load, args.serve_warm)
     cpu = None
     if not args.no_cpu_baseline:
         print("bench: cpu baseline (oracle)", file=sys.stderr, flush=True)
-        cpu = cpu_baseline(wl, args.cpu_budget, threads=args.cpu_threads)
+        cpu = cpu_baseline(threads=args.cpu_threads)
+    hbm64, alu64 = rooflines(r64, "k_step3_fp64", wname)
     line = {
         "metric": METRIC,
         "value": r64["value"],
@@ -295,12 +425,10 @@ def main():
                    "grid": [args.nper] * 3, "angles": r64["nang"], "courant": 0.4,
                    "kappa_a": 0.1, "kappa_s": 1.0, "launch": {"blocks": r64["grid_blocks"],
                                                               "threads": r64["block_threads"]}},
-        "roofline": {"bound": "hbm", "achieved": r64["achieved_gbs"], "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": r64["achieved_gbs"] / HBM_PEAK_GBS,
-                     "traffic": load_traffic("k_step3_fp64", wname),
-                     "kernel": "rtk::k_step3<double, double, 10, 1, true, true>",
-                     "kernel_ms": r64["kernel_ms"], "bytes_per_launch": r64["bytes_per_launch"]},
+        "roofline": hbm64,
+        "compute_roofline": alu64,
         "fp32_mixed": mixed,
+        "fp32_mixed_other_workloads": others,
         "serving": srv,
         "cpu_baseline": cpu,
     }
