@@ -96,7 +96,8 @@ def kernel_name(info, storage_bytes: int) -> str:
     waves = max(1, info["block_threads"] // 64)
     ng = -(-info["nang"] // 10)
     groups = -(-ng // waves)
-    return f"rtk::k_step3<{t}, {t}, 10, {groups}, true, true>"
+    per = "true" if info.get("periodic", True) else "false"
+    return f"rtk::k_step3<{t}, {t}, 10, {groups}, {per}, true>"
 
 
 def rooflines(r, tag: str, wname: str):
@@ -163,7 +164,8 @@ def run_gpu(wl, precision: str, steps: int, warmup: int, second_order: bool = Fa
                 launches=nl, bytes_per_launch=bpl, achieved_gbs=bpl / kavg / 1e9,
                 nang=info.nang, storage_bytes=info.storage_bytes, totals=totals,
                 grid_blocks=info.grid_blocks, block_threads=info.block_threads,
-                updates_per_launch=wl.ncell * info.nang)
+                updates_per_launch=wl.ncell * info.nang,
+                periodic=all(b[0] == 0 for b in wl.bc[:wl.ndim]))
 
 
 def _host_cpu():
