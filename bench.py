@@ -242,19 +242,24 @@ def configs_leg(steps: int = 5, warmup: int = 2):
     return out
 
 
-SERVE_DEFAULTS = dict(pool_bytes=96 << 30, max_active=1024, packed_cells=4096,
+# A packed solve runs on one workgroup: beyond about 512 cells its single CU,
+# not the device, sets its latency (packed requests of up to 4096 cells had a
+# median latency of 0.5 s on the 200-request trace at load 0.8, against 20 ms
+# at 512).
+SERVE_DEFAULTS = dict(pool_bytes=96 << 30, max_active=1024, packed_cells=512,
                       chunk_work=400_000_000, large_work=40_000_000)
 
 
-def serving(count: int, load: float, warm: int, seed: int = 4, fifo: bool = True):
+def serving(count: int, loads, warm: int, seed: int = 4, fifo: bool = True):
     """The serving stream: `count` requests of the mixed-size trace (1D/2D/3D
     grids of 64 to 128^3 cells log-uniform, 16-288 directions, 10-200 steps,
     FP32-mixed, Poisson arrivals).  The batched capacity is measured first in
-    a closed loop over the first `warm` requests; arrivals are then scaled so
-    that the offered load is `load` times that capacity, and the same trace
-    runs through the server and through the plain one-at-a-time path.  The
+    a closed loop over the first `warm` requests; for each offered load (times
+    that capacity) the arrivals are scaled to it and the same trace runs
+    through the server and through the plain one-at-a-time path.  The
     capacity run takes the whole trace by default: a prefix of a heavy-tailed
-    mix need not carry its mean cost."""
+    mix need not carry its mean cost.  Latencies are also given per request
+    class (packed, chunked, large)."""
     import numpy as np
     import torch
 
@@ -271,23 +276,29 @@ def serving(count: int, load: float, warm: int, seed: int = 4, fifo: bool = True
     say(f"{count} requests generated")
     warm = warm if 0 < warm < count else count
     cap = serve.run_batched(wls[:warm], [0.0] * warm, progress=say, **SERVE_DEFAULTS)
-    rate = load * cap["throughput"] / work.mean()          # requests per second
-    arrivals = np.cumsum([r["gap"] for r in reqs]) / rate
-    arrivals -= arrivals[0]
-    print(f"bench: serving capacity {cap['throughput']:.3g} updates/s, offered "
-          f"{rate:.3g} req/s over {arrivals[-1]:.1f} s", file=sys.stderr, flush=True)
-    b = serve.run_batched(wls, arrivals, progress=say, **SERVE_DEFAULTS)
-    print(f"bench: served p50 {b['latency_p50_s']*1e3:.1f} ms p99 {b['latency_p99_s']*1e3:.1f} ms "
-          f"{b['throughput']:.3g} updates/s", file=sys.stderr, flush=True)
-    torch.cuda.empty_cache()
-    f = None
-    if fifo:
-        f = serve.run_fifo(wls, arrivals, progress=say)
-        print(f"bench: fifo p50 {f['latency_p50_s']*1e3:.1f} ms p99 {f['latency_p99_s']*1e3:.1f} ms "
-              f"{f['throughput']:.3g} updates/s", file=sys.stderr, flush=True)
-    return dict(requests=count, load=load, closed_loop_capacity=cap["throughput"],
-                offered_req_per_s=rate, mean_updates_per_request=float(work.mean()),
-                batched=b, fifo=f, server=SERVE_DEFAULTS,
+    runs = {}
+    for load in loads:
+        rate = load * cap["throughput"] / work.mean()          # requests per second
+        arrivals = np.cumsum([r["gap"] for r in reqs]) / rate
+        arrivals -= arrivals[0]
+        print(f"bench: serving capacity {cap['throughput']:.3g} updates/s, load {load}: offered "
+              f"{rate:.3g} req/s over {arrivals[-1]:.1f} s", file=sys.stderr, flush=True)
+        b = serve.run_batched(wls, arrivals, progress=say, **SERVE_DEFAULTS)
+        print(f"bench: served p50 {b['latency_p50_s']*1e3:.1f} ms p99 "
+              f"{b['latency_p99_s']*1e3:.1f} ms {b['throughput']:.3g} updates/s", file=sys.stderr,
+              flush=True)
+        torch.cuda.empty_cache()
+        f = None
+        if fifo:
+            f = serve.run_fifo(wls, arrivals, progress=say,
+                               packed_cells=SERVE_DEFAULTS["packed_cells"],
+                               large_work=SERVE_DEFAULTS["large_work"])
+            print(f"bench: fifo p50 {f['latency_p50_s']*1e3:.1f} ms p99 "
+                  f"{f['latency_p99_s']*1e3:.1f} ms {f['throughput']:.3g} updates/s",
+                  file=sys.stderr, flush=True)
+        runs[f"load_{load}"] = dict(load=load, offered_req_per_s=rate, batched=b, fifo=f)
+    return dict(requests=count, closed_loop_capacity=cap["throughput"],
+                mean_updates_per_request=float(work.mean()), runs=runs, server=SERVE_DEFAULTS,
                 latency="submission to results in host memory")
 
 
@@ -321,14 +332,24 @@ def main():
                          "(the thread-per-cell kernel)")
     ap.add_argument("--serve-requests", type=int, default=200,
                     help="requests of the serving trace (0: skip; 2000 = the full stream)")
-    ap.add_argument("--serve-load", type=float, default=0.8)
+    ap.add_argument("--serve-load", type=float, nargs="+", default=[0.8, 1.2],
+                    help="offered loads relative to the closed-loop capacity (the trace is "
+                         "replayed at each)")
     ap.add_argument("--serve-warm", type=int, default=0,
                     help="requests of the closed-loop capacity run (0: the whole trace)")
     ap.add_argument("--only-serve", action="store_true")
+    ap.add_argument("--serve-packed-cells", type=int, default=SERVE_DEFAULTS["packed_cells"],
+                    help="largest FP32 request (cells) run in packed persistent launches")
+    ap.add_argument("--serve-large-work", type=int, default=SERVE_DEFAULTS["large_work"],
+                    help="updates per step from which a request takes the large stream")
+    ap.add_argument("--serve-chunk-work", type=int, default=SERVE_DEFAULTS["chunk_work"],
+                    help="cell-angle updates per chunked launch group")
     ap.add_argument("--copy-probe", type=float, default=0.0,
                     help="profiling: time a plain device-to-device copy of this many GiB "
                          "(counter calibration) and exit")
     args = ap.parse_args()
+    SERVE_DEFAULTS.update(packed_cells=args.serve_packed_cells, large_work=args.serve_large_work,
+                          chunk_work=args.serve_chunk_work)
     if args.second_order and not args.only:
         ap.error("--second-order goes with --only")
     if args.gpus != 1:

@@ -41,7 +41,7 @@ class Server:
     """One serving runtime on the current GPU (see ``include/rt_serve.h``)."""
 
     def __init__(self, pool_bytes: int = 32 << 30, max_active: int = 1024,
-                 packed_cells: int = 4096, chunk_work: int = 200_000_000,
+                 packed_cells: int = 512, chunk_work: int = 200_000_000,
                  large_work: int = 20_000_000):
         self.srv = rt.rt_serve_create(int(pool_bytes), int(max_active), int(packed_cells),
                                       int(chunk_work), int(large_work))
@@ -128,6 +128,24 @@ def _percentiles(lat: Sequence[float]) -> Dict[str, float]:
                 mean=float(x.mean()), max=float(x.max()))
 
 
+def request_class(wl, nang: int, packed_cells: int, large_work: int) -> str:
+    """The server's class of a request: 'packed' (FP32-mixed, at most
+    packed_cells cells: one workgroup per solve), 'large' (at least
+    large_work updates per step: the large-request stream), else 'chunked'."""
+    if wl.precision == "mixed" and wl.ncell <= packed_cells:
+        return "packed"
+    return "large" if wl.ncell * nang >= large_work else "chunked"
+
+
+def _by_class(lat: Sequence[float], classes: Sequence[str]) -> Dict[str, Dict]:
+    out = {}
+    for c in ("packed", "chunked", "large"):
+        x = [l for l, k in zip(lat, classes) if k == c]
+        if x:
+            out[c] = dict(count=len(x), **_percentiles(x))
+    return out
+
+
 def run_batched(wls: List, arrivals: Sequence[float], progress=None, **server_kw) -> Dict:
     """Replays the trace against the server: request i is submitted at
     arrivals[i] seconds after the start; returns latencies (submission to
@@ -162,17 +180,22 @@ def run_batched(wls: List, arrivals: Sequence[float], progress=None, **server_kw
                chunk_launches=counters["chunk_launches"],
                packed_launches=counters["packed_launches"])
     out.update({f"latency_{k}_s": v for k, v in _percentiles(lat).items()})
+    classes = [request_class(h.wl, h.nang, server_kw.get("packed_cells", 4096),
+                             server_kw.get("large_work", 20_000_000)) for h in handles]
+    out["latency_by_class_s"] = _by_class(lat, classes)
     return out
 
 
-def run_fifo(wls: List, arrivals: Sequence[float], progress=None) -> Dict:
+def run_fifo(wls: List, arrivals: Sequence[float], progress=None, packed_cells: int = 512,
+             large_work: int = 20_000_000) -> Dict:
     """The same trace through the plain path: one request at a time in
     arrival order, each created, uploaded, stepped with rt_step, copied back
-    and destroyed before the next starts."""
+    and destroyed before the next starts.  Latencies are also grouped by the
+    class the server would give each request."""
     import torch
     dev = torch.device("cuda")
     stream = torch.cuda.current_stream().cuda_stream
-    lat, t_first, t_last, work = [], None, 0.0, 0.0
+    lat, classes, t_first, t_last, work = [], [], None, 0.0, 0.0
     t0 = time.perf_counter()
     for i, wl in enumerate(wls):
         arrive = t0 + arrivals[i]
@@ -207,6 +230,7 @@ def run_fifo(wls: List, arrivals: Sequence[float], progress=None) -> Dict:
         t_first = arrive if t_first is None else t_first
         t_last = done
         lat.append(done - arrive)
+        classes.append(request_class(wl, nang, packed_cells, large_work))
         work += float(nc) * nang * wl.nsteps
         del T_h, E_h, F_h, tot_h
         if progress and (i + 1) % 50 == 0:
@@ -214,4 +238,5 @@ def run_fifo(wls: List, arrivals: Sequence[float], progress=None) -> Dict:
     out = dict(requests=len(wls), makespan_s=t_last - t_first, updates=work,
                throughput=work / (t_last - t_first))
     out.update({f"latency_{k}_s": v for k, v in _percentiles(lat).items()})
+    out["latency_by_class_s"] = _by_class(lat, classes)
     return out
