@@ -395,8 +395,8 @@ def main():
         return
     wl = W.config2(nper=args.nper)
     wname = f"box3d_{args.nper}cube_S8"
-    print(f"bench: {wname} fp64 warmup={args.warmup} steps={args.steps}", file=sys.stderr,
-          flush=True)
+    print(f"bench: {wname} {args.only or 'fp64'} warmup={args.warmup} steps={args.steps}",
+          file=sys.stderr, flush=True)
     if args.only:
         r = run_gpu(wl, args.only, args.steps, args.warmup, second_order=args.second_order)
         print(json.dumps({"precision": args.only, "second_order": args.second_order,

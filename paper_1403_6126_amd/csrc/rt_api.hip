@@ -153,9 +153,9 @@ bool fields_ok(const rt_fields *f) {
 void launch_step(const rt_ctx *c, const StepArgs &a, bool fused, hipStream_t s) {
   clear_stale_error();
   if (c->p.precision == RT_FP32_MIXED)
-    launch_step_f32(a, c->shape, fused, ctx_step_blocks(c), s);
+    launch_step_f32(a, c->shape, fused, ctx_step_blocks(c, fused), s);
   else
-    launch_step_f64(a, c->shape, fused, ctx_step_blocks(c), s);
+    launch_step_f64(a, c->shape, fused, ctx_step_blocks(c, fused), s);
 }
 
 void launch_transport(const rt_ctx *c, const StepArgs &a, hipStream_t s) {
@@ -209,6 +209,7 @@ int one_step(rt_ctx *c, double dt, const rt_fields *f, const void *dF, bool fuse
   a.mom_in = c->mom[c->mom_cur];
   a.mom_out = c->mom[1 - c->mom_cur];
   a.dF_in = dF;
+  a.nparts = (int)ctx_step_blocks(c, fused);
   a.accumulate = first ? 0 : 1;
   if (o) {
     a.dEgas = o->dEgas;
@@ -233,7 +234,7 @@ int one_step(rt_ctx *c, double dt, const rt_fields *f, const void *dF, bool fuse
   }
   if (last && o && o->totals) {
     hipLaunchKernelGGL(k_totals, dim3(1), dim3(kVLanes), 0, s, c->partials,
-                       (int)ctx_step_blocks(c), o->totals);
+                       a.nparts, o->totals);
     if (!hip_ok(hipGetLastError())) return RT_EDEVICE;
   }
   c->cur = 1 - c->cur;
@@ -244,8 +245,11 @@ int one_step(rt_ctx *c, double dt, const rt_fields *f, const void *dF, bool fuse
 
 }  // namespace
 
-long long ctx_step_blocks(const rt_ctx *c) {
-  return c->shape.waves ? (c->ncell + 63) / 64 : (c->ncell + kBlock - 1) / kBlock;
+long long ctx_step_blocks(const rt_ctx *c, bool fused) {
+  // the wave-group kernel works in tiles of 64 cells; a second-order step
+  // from a given dF runs on the thread-per-cell kernel
+  const bool tiles = c->shape.waves && (fused || !c->shape.second);
+  return tiles ? (c->ncell + 63) / 64 : (c->ncell + kBlock - 1) / kBlock;
 }
 
 int ctx_storage_bytes(const rt_ctx *c) { return c->p.precision == RT_FP32_MIXED ? 4 : 8; }
@@ -315,7 +319,7 @@ void ctx_fill_args(const rt_ctx *c, double dt_call, const rt_fields *f, StepArgs
   }
   a.status = c->status;
   a.partials = c->partials;
-  a.nparts = (int)ctx_step_blocks(c);
+  a.nparts = (int)ctx_step_blocks(c, true);
 }
 
 int ctx_init_host(const rt_grid *g, const rt_angles *an, const rt_params *p, rt_ctx *c) {
@@ -376,11 +380,9 @@ int ctx_init_host(const rt_grid *g, const rt_angles *an, const rt_params *p, rt_
     if (s > c->cfl_sum) c->cfl_sum = s;
   }
   c->shape = pick_shape(N, c->all_periodic, p->precision);
-  if (p->flags & RT_SECOND_ORDER) {
-    // the second absorption solve runs on the thread-per-cell kernel
-    c->shape.waves = c->shape.groups = 0;
-    c->shape.second = true;
-  }
+  // second order: the fused step runs both absorption solves on the
+  // wave-group kernel; the step from a given dF on the thread-per-cell one
+  if (p->flags & RT_SECOND_ORDER) c->shape.second = true;
   c->nblocks = (nc + 63) / 64;  // enough partial-total rows for either kernel
   // angle records: every slot of the wave-group kernel has one
   // (the packed serving kernel runs the same groups on kMaxWaves waves)
@@ -821,7 +823,7 @@ int rt_get_info(rt_ctx *c, rt_info *info) {
   info->ncell = c->ncell;
   info->storage_bytes = ctx_storage_bytes(c);
   info->block_threads = c->shape.waves ? 64 * c->shape.waves : kBlock;
-  info->grid_blocks = ctx_step_blocks(c);
+  info->grid_blocks = ctx_step_blocks(c, true);
   return RT_OK;
 }
 

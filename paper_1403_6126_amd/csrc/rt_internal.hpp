@@ -22,7 +22,7 @@ constexpr int kMaxGroupsPerWave = 4;
 struct KShape {
   int waves = 0, groups = 0;
   bool periodic = true;
-  bool second = false;  // second-order absorption (thread-per-cell kernel only)
+  bool second = false;  // second-order absorption (both solves in the step)
 };
 
 // One request of a packed persistent launch: a whole solve of nsteps steps
@@ -117,7 +117,7 @@ int ctx_prepare_call(rt_ctx *c, double dt, const rt_fields *f, hipStream_t s);
 void ctx_fill_args(const rt_ctx *c, double dt, const rt_fields *f, StepArgs &a);
 // I[m][c] = T[c]^4 / (4 pi) for every angle (storage type of the context).
 int ctx_init_equilibrium(rt_ctx *c, const double *T, void *I, hipStream_t s);
-long long ctx_step_blocks(const rt_ctx *c);
+long long ctx_step_blocks(const rt_ctx *c, bool fused);
 int ctx_storage_bytes(const rt_ctx *c);
 int ctx_check_dt(const rt_ctx *c, double dt);
 

@@ -572,7 +572,7 @@ int rt_serve_submit(rt_server *s, const rt_request *r, long long *id) {
   const double per_step = (double)q->ctx.ncell * (double)N;
   q->work = per_step * r->nsteps;
   q->packed = r->params.precision == RT_FP32_MIXED && q->ctx.ncell <= s->cfg.packed_cells &&
-              q->ctx.shape.waves > 0;
+              q->ctx.shape.waves > 0 && !q->ctx.shape.second;
   q->large = per_step >= (double)s->cfg.large_work;
   q->chunk = (int)std::max(1.0, std::min((double)r->nsteps, (double)s->cfg.chunk_work / per_step));
   std::lock_guard<std::mutex> lk(s->mu);

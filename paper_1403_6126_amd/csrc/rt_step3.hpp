@@ -289,10 +289,47 @@ __host__ __device__ constexpr size_t step3_lds_bytes(int G) {
   return sizeof(double) * ((size_t)G * kChunk * 64 + kChunk * 64 + 6 * 64);
 }
 
+// The reduced absorption system of one cell (Section 4.3, Eq.
+// absorptionmatrix): from the angle sums S[0..8] (sum W r/D, W e/D, W/D,
+// the same weighted by n.u and by u^2 + (n.u)^2) the temperature equation is
+// one quartic, c_v (T' - T^n) = h0 + h1q T'^4, solved by Newton's method in
+// FP64 from T^n; returns T' and sets X = T'^4/(4 pi), Q (the n.u-weighted
+// intensity sum of the solution), the iteration count and convergence.
+template <int NV>
+__device__ __forceinline__ double absorb_solve(const StepArgs &p, const double (&S)[NV], double kap,
+                                               double uu, double cv, double Tn, double sa,
+                                               double &X, double &Q, int &it, bool &conv) {
+  const double C = p.C, P = p.P, dt = p.dt, iC = p.invC;
+  const double qden = 1.0 + kap * S[8];
+  const double iqden = fast_rcp(qden);
+  const double q0 = S[6] * iqden, q1 = S[7] * iqden;
+  const double j0 = S[0] - kap * S[2] * q0, j1 = S[1] - kap * S[2] * q1;
+  const double k0 = S[3] - kap * S[5] * q0, k1 = S[4] - kap * S[5] * q1;
+  const double beta = P * C * (1.0 - uu * iC * iC) * sa * dt;
+  const double g8 = 8.0 * kPi * P * sa * dt;
+  const double h0 = -g8 * (k0 - q0 * iC) + kFourPi * beta * j0;
+  const double h1q = (-g8 * (k1 - q1 * iC) - kFourPi * beta * (1.0 - j1)) * (1.0 / kFourPi);
+  double T = Tn;
+  conv = false;
+  for (it = 1; it <= p.maxit; ++it) {
+    const double T3 = T * T * T;
+    const double f = cv * (T - Tn) - h0 - h1q * T3 * T;
+    const double dT = f * fast_rcp(cv - 4.0 * h1q * T3);
+    T -= dT;
+    if (fabs(dT) <= p.rtol * fabs(T)) {
+      conv = true;
+      break;
+    }
+  }
+  X = T * T * T * T * (1.0 / kFourPi);
+  Q = q0 + q1 * X;
+  return T;
+}
+
 // One step for the 64 cells of tile blk (cells blk*64 + lane), G waves.
 // Writes I^{n+1}, the moments and the outputs of those cells and the tile's
 // partial totals into row blk of p.partials.
-template <typename S, typename A, int KA, int NG, bool PER, bool FUSED>
+template <typename S, typename A, int KA, int NG, bool PER, bool FUSED, bool SO = false>
 __device__ __forceinline__ void step3_tile(const StepArgs &p, int blk, int G, double *lds) {
   constexpr int NS = KA * NG;  // angle slots of a wave: slot j*KA + k
   double *sbuf = lds, *stot = lds + (size_t)G * kChunk * 64, *ssol = stot + kChunk * 64;
@@ -488,6 +525,78 @@ __device__ __forceinline__ void step3_tile(const StepArgs &p, int blk, int G, do
   const A B0 = A(-dt * C * ss - dt * ss * uu * iC), dssC = A(dt * ss * iC);
   // the routing as factors: r4 = I + g4 dF, p = r4/D + g5 dF
   const A g4 = to5 ? A(0) : A(1), g5 = to5 ? A(1) : A(0);
+  const double kap = dt * sa * iC;
+  const double cv = rho * p.cvfac;
+  auto cell_ic = [&](int k) -> A {
+    return IC_REG ? Ic[IC_REG ? k : 0] : A(plane_ld(slot_plane(k), (unsigned)c));
+  };
+
+  // SO: the absorption system is first solved at u alone (its sums and, for
+  // the momentum change of that solution, sum W n (I' - r4) in closed form
+  // from I'_m - r4_m = (-dt sa (C - t) r4_m + e_m X - kappa Q)/D_m), which
+  // gives the time-centred velocity uc = v + d4/(2 rho) (d4 as the gas sees
+  // it); the step's absorption coefficients are then taken at uc, the
+  // scattering ones at u.
+  double ua0 = u0, ua1 = u1, ua2 = u2, uua = uu;
+  int it_first = 0;
+  bool conv_first = true;
+  if constexpr (SO) {
+    A s1a[9], hm[9];
+#pragma unroll
+    for (int r = 0; r < 9; ++r) s1a[r] = hm[r] = A(0);
+    const A AC = A(C);
+#pragma unroll
+    for (int k = 0; k < NS; ++k) {
+      if (slot_m(k) >= NA) continue;
+      const A *R = slot_rec(k);
+      const A n0 = R[rec_n0], n1 = R[rec_n1], n2 = R[rec_n2];
+      const A t = n0 * Au0 + n1 * Au1 + n2 * Au2;
+      const A invD = fast_rcp(D0 - dsa * t);
+      const A e = E0 + A(3) * dsa * t;
+      const A gg = Auu + t * t;
+      const A r4 = cell_ic(k) + g4 * dF[k];
+      const A WD = R[rec_w] * invD;
+      s1a[0] += WD * r4;
+      s1a[1] += WD * e;
+      s1a[2] += WD;
+      s1a[3] += WD * t * r4;
+      s1a[4] += WD * t * e;
+      s1a[5] += WD * t;
+      s1a[6] += WD * gg * r4;
+      s1a[7] += WD * gg * e;
+      s1a[8] += WD * gg;
+      const A wr = -(WD * dsa * (AC - t) * r4), we = WD * e;
+      const A nn[3] = {n0, n1, n2};
+#pragma unroll
+      for (int q = 0; q < 3; ++q) {
+        hm[q] += nn[q] * wr;
+        hm[3 + q] += nn[q] * we;
+        hm[6 + q] += nn[q] * WD;
+      }
+    }
+    double S1[9], H[9];
+#pragma unroll
+    for (int r = 0; r < 9; ++r) {
+      S1[r] = double(s1a[r]);
+      H[r] = double(hm[r]);
+    }
+    waves_reduce<9, false, kChunk>(S1, sbuf, stot, g, G, lane);
+    waves_reduce<9, false, kChunk>(H, sbuf, stot, g, G, lane);
+    double X1, Q1;
+    bool ok1;
+    int it1;
+    absorb_solve(p, S1, kap, uu, cv, Tn, sa, X1, Q1, it1, ok1);
+    it_first = it1;
+    conv_first = ok1;
+    // the Step 4 momentum change of the first solution, as the gas sees it
+    const double fm = -p.gasfac * kFourPi * P * iC, h2r = 0.5 * fast_rcp(rho);
+    ua0 = v0 + fm * (H[0] + X1 * H[3] - kap * Q1 * H[6]) * h2r;
+    ua1 = v1 + fm * (H[1] + X1 * H[4] - kap * Q1 * H[7]) * h2r;
+    ua2 = v2 + fm * (H[2] + X1 * H[5] - kap * Q1 * H[8]) * h2r;
+    uua = ua0 * ua0 + ua1 * ua1 + ua2 * ua2;
+  }
+  const A Ua0 = A(ua0), Ua1 = A(ua1), Ua2 = A(ua2), Auua = A(uua);
+
   A pk[NS];
   A sm[kNsum];
 #pragma unroll
@@ -500,15 +609,16 @@ __device__ __forceinline__ void step3_tile(const StepArgs &p, int blk, int G, do
     const A *R = slot_rec(k);
     const A n0 = R[rec_n0], n1 = R[rec_n1], n2 = R[rec_n2];
     const A Wm = R[rec_w];
-    const A t = n0 * Au0 + n1 * Au1 + n2 * Au2;
-    const A D = D0 - dsa * t, aw = AW0 - dss * t;
+    const A t = n0 * Au0 + n1 * Au1 + n2 * Au2;  // scattering: at u
+    const A ta = SO ? n0 * Ua0 + n1 * Ua1 + n2 * Ua2 : t;  // absorption
+    const A D = D0 - dsa * ta, aw = AW0 - dss * t;
     const A rDa = fast_rcp(D * aw);
     const A invD = aw * rDa, invaw = D * rDa;
-    const A e = E0 + A(3) * dsa * t;
-    const A gg = Auu + t * t;
+    const A e = E0 + A(3) * dsa * ta;
+    const A gg = (SO ? Auua : Auu) + ta * ta;
     const A b = B0 + A(2) * dss * t - dssC * t * t;
     const A cm = A(-3) * dss * t;
-    const A ick = IC_REG ? Ic[IC_REG ? k : 0] : A(plane_ld(slot_plane(k), (unsigned)c));
+    const A ick = cell_ic(k);
     const A r4 = ick + g4 * dF[k];
     const A pm = r4 * invD + g5 * dF[k];
     pk[k] = pm;
@@ -516,9 +626,9 @@ __device__ __forceinline__ void step3_tile(const StepArgs &p, int blk, int G, do
     sm[0] += WD * r4;
     sm[1] += WD * e;
     sm[2] += WD;
-    sm[3] += WD * t * r4;
-    sm[4] += WD * t * e;
-    sm[5] += WD * t;
+    sm[3] += WD * ta * r4;
+    sm[4] += WD * ta * e;
+    sm[5] += WD * ta;
     sm[6] += WD * gg * r4;
     sm[7] += WD * gg * e;
     sm[8] += WD * gg;
@@ -551,35 +661,17 @@ __device__ __forceinline__ void step3_tile(const StepArgs &p, int blk, int G, do
   // Every wave holds the reduced sums of its 64 cells, so every wave can
   // solve them (RT_SOLVE_ALL, no barrier and no idle waves), or wave 0
   // solves and passes the solution on through LDS.
-  const double kap = dt * sa * iC;
-  const double cv = rho * p.cvfac;
   double X = 0.0, kQ = 0.0, s1 = 0.0, s2 = 0.0, T = 0.0, newton_it = 0.0;
   if (RT_SOLVE_ALL || g == 0) {
-    const double qden = 1.0 + kap * Sa[8];
-    const double iqden = fast_rcp(qden);
-    const double q0 = Sa[6] * iqden, q1 = Sa[7] * iqden;
-    const double j0 = Sa[0] - kap * Sa[2] * q0, j1 = Sa[1] - kap * Sa[2] * q1;
-    const double k0 = Sa[3] - kap * Sa[5] * q0, k1 = Sa[4] - kap * Sa[5] * q1;
-    const double beta = P * C * (1.0 - uu * iC * iC) * sa * dt;
-    const double g8 = 8.0 * kPi * P * sa * dt;
-    const double h0 = -g8 * (k0 - q0 * iC) + kFourPi * beta * j0;
-    const double h1q = (-g8 * (k1 - q1 * iC) - kFourPi * beta * (1.0 - j1)) * (1.0 / kFourPi);
-    double Tt = Tn;
+    double Q;
     int it;
-    bool conv = false;
-    for (it = 1; it <= p.maxit; ++it) {
-      const double T3 = Tt * Tt * Tt;
-      const double f = cv * (Tt - Tn) - h0 - h1q * T3 * Tt;
-      const double dT = f * fast_rcp(cv - 4.0 * h1q * T3);
-      Tt -= dT;
-      if (fabs(dT) <= p.rtol * fabs(Tt)) {
-        conv = true;
-        break;
-      }
+    bool conv;
+    T = absorb_solve(p, Sa, kap, SO ? uua : uu, cv, Tn, sa, X, Q, it, conv);
+    if (SO) {
+      it = it > it_first ? it : it_first;
+      conv = conv && conv_first;
     }
-    if (g == 0 && act && (!conv || !(Tt > 0.0) || !isfinite(Tt))) atomicOr(p.status, 1);
-    X = Tt * Tt * Tt * Tt * (1.0 / kFourPi);
-    const double Q = q0 + q1 * X;
+    if (g == 0 && act && (!conv || !(T > 0.0) || !isfinite(T))) atomicOr(p.status, 1);
     const double Sbr = Sa[9] + X * Sb[4] - kap * Q * Sb[5];
     const double Sr5 = Sa[10] + X * Sb[6] - kap * Q * Sb[7];
     const double a11 = 1.0 + Sb[0], a12 = Sb[1], a21 = Sb[2], a22 = 1.0 + Sb[3];
@@ -588,7 +680,6 @@ __device__ __forceinline__ void step3_tile(const StepArgs &p, int blk, int G, do
     kQ = kap * Q;
     s1 = (Sbr * a22 - a12 * Sr5) * idet;
     s2 = (a11 * Sr5 - a21 * Sbr) * idet;
-    T = Tt;
     newton_it = double(it);
   }
   if constexpr (!RT_SOLVE_ALL) {
@@ -631,9 +722,10 @@ __device__ __forceinline__ void step3_tile(const StepArgs &p, int blk, int G, do
     if (m >= NA) continue;
     const A *R = slot_rec(k);
     const A t = R[rec_n0] * Au0 + R[rec_n1] * Au1 + R[rec_n2] * Au2;
-    const A D = D0 - dsa * t, aw = AW0 - dss * t;
+    const A ta = SO ? R[rec_n0] * Ua0 + R[rec_n1] * Ua1 + R[rec_n2] * Ua2 : t;
+    const A D = D0 - dsa * ta, aw = AW0 - dss * t;
     const A rDa = fast_rcp(D * aw);
-    const A e = E0 + A(3) * dsa * t;
+    const A e = E0 + A(3) * dsa * ta;
     const A cm = A(-3) * dss * t;
     // I' = invaw (p - s1 - c s2) + invD invaw (e X - kappa Q)
     const S Inew = S(D * rDa * (pk[k] - As1 - cm * As2) + rDa * (e * AX - AkQ));
@@ -769,7 +861,7 @@ __device__ __forceinline__ void step3_tile(const StepArgs &p, int blk, int G, do
 #define RT_BLOCK_ORDER_F32 2
 #endif
 
-template <typename S, typename A, int KA, int NG, bool PER, bool FUSED>
+template <typename S, typename A, int KA, int NG, bool PER, bool FUSED, bool SO = false>
 __global__ __launch_bounds__(64 * kMaxWaves, sizeof(S) == 8 ? RT_STEP3_WAVES_F64
                                                             : RT_STEP3_WAVES_F32) void
 k_step3(StepArgs p) {
@@ -777,7 +869,7 @@ k_step3(StepArgs p) {
   constexpr int ORD = sizeof(S) == 8 ? RT_BLOCK_ORDER_F64 : RT_BLOCK_ORDER_F32;
   const int b = (int)blockIdx.x, nb = (int)gridDim.x;
   const int blk = ORD == 2 ? slab_block(b, nb, p.n) : ORD == 1 ? xcd_block(b, nb) : b;
-  step3_tile<S, A, KA, NG, PER, FUSED>(p, blk, blockDim.x >> 6, lds_);
+  step3_tile<S, A, KA, NG, PER, FUSED, SO>(p, blk, blockDim.x >> 6, lds_);
 }
 
 // A whole solve per workgroup: job blockIdx.x advances its grid through
