@@ -123,7 +123,7 @@ size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 #define RT_GROUP_WAVES_F64 4
 #endif
 #ifndef RT_GROUP_WAVES_F32
-#define RT_GROUP_WAVES_F32 8
+#define RT_GROUP_WAVES_F32 4
 #endif
 
 KShape pick_shape(int nang, bool periodic, int precision) {
@@ -384,9 +384,9 @@ int ctx_init_host(const rt_grid *g, const rt_angles *an, const rt_params *p, rt_
   // wave-group kernel; the step from a given dF on the thread-per-cell one
   if (p->flags & RT_SECOND_ORDER) c->shape.second = true;
   c->nblocks = (nc + 63) / 64;  // enough partial-total rows for either kernel
-  // angle records: every slot of the wave-group kernel has one
-  // (the packed serving kernel runs the same groups on kMaxWaves waves)
-  const int slots = c->shape.waves ? kMaxWaves * c->shape.groups * kAnglesPerWave : 0;
+  // angle records: every slot of the wave-group kernel has one (padding
+  // slots a zero record)
+  const int slots = c->shape.waves * c->shape.groups * kAnglesPerWave;
   c->nrec = slots > N ? slots : N;
   return RT_OK;
 }

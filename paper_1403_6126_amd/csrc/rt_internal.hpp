@@ -41,13 +41,14 @@ hipError_t launch_step_f64(const StepArgs &a, const KShape &k, bool fused, long 
                            hipStream_t s);
 hipError_t launch_step_f32(const StepArgs &a, const KShape &k, bool fused, long long blocks,
                            hipStream_t s);
-// Packed persistent launches: one workgroup of 64*kMaxWaves threads per job;
-// every job of a launch has `groups` angle groups per wave and the given
-// boundary class.
-hipError_t launch_packed_f64(const PackedJob *jobs, int njobs, int groups, bool periodic,
-                             hipStream_t s);
-hipError_t launch_packed_f32(const PackedJob *jobs, int njobs, int groups, bool periodic,
-                             hipStream_t s);
+// Packed persistent launches: one workgroup of 64*waves threads per job;
+// every job of a launch has the launch shape (waves, groups) of its own
+// context, so that it sums its angles in the order rt_step does, and the
+// given boundary class.
+hipError_t launch_packed_f64(const PackedJob *jobs, int njobs, int waves, int groups,
+                             bool periodic, hipStream_t s);
+hipError_t launch_packed_f32(const PackedJob *jobs, int njobs, int waves, int groups,
+                             bool periodic, hipStream_t s);
 
 }  // namespace rtk
 

@@ -388,13 +388,14 @@ void rt_server::sched_loop() {
         }
       if (slot < 0) break;
       const int groups = to_pack.front()->ctx.shape.groups;
+      const int waves = to_pack.front()->ctx.shape.waves;
       const bool per = to_pack.front()->ctx.all_periodic;
       Batch b;
       b.slot = slot;
       std::vector<Request *> rest;
       for (Request *q : to_pack) {
         if ((int)b.reqs.size() < kMaxBatch && q->ctx.shape.groups == groups &&
-            q->ctx.all_periodic == per)
+            q->ctx.shape.waves == waves && q->ctx.all_periodic == per)
           b.reqs.push_back(q);
         else
           rest.push_back(q);
@@ -420,7 +421,7 @@ void rt_server::sched_loop() {
       }
       bool ok = hipMemcpyAsync(dj, hj, sizeof(PackedJob) * b.reqs.size(), hipMemcpyHostToDevice,
                                s_pack) == hipSuccess;
-      ok = ok && launch_packed_f32(dj, (int)b.reqs.size(), groups, per, s_pack) == hipSuccess;
+      ok = ok && launch_packed_f32(dj, (int)b.reqs.size(), waves, groups, per, s_pack) == hipSuccess;
       b.ev = new_event();
       ok = ok && b.ev && hipEventRecord(b.ev, s_pack) == hipSuccess;
       slot_busy[slot] = true;

@@ -873,9 +873,9 @@ k_step3(StepArgs p) {
 }
 
 // A whole solve per workgroup: job blockIdx.x advances its grid through
-// nsteps fused steps, tile by tile (64 cells per tile, kMaxWaves waves, the
-// same step body as k_step3, hence the same per-cell results and partial
-// totals), and reduces the partial totals after the last step like
+// nsteps fused steps, tile by tile (64 cells per tile, the waves of the
+// context's launch shape, the same step body as k_step3, hence the same
+// per-cell results and partial totals), and reduces the partial totals after the last step like
 // k_totals.  Between steps the workgroup fences its global writes (I,
 // moments, T, partials) before any wave reads them.
 template <typename S, typename A, int KA, int NG, bool PER>
@@ -900,7 +900,7 @@ __global__ __launch_bounds__(64 * kMaxWaves) void k_step3_packed(
     p.oF = last ? oF : nullptr;
     p.oP = last ? oP : nullptr;
     for (int t = 0; t < ntiles; ++t)
-      step3_tile<S, A, KA, NG, PER, true>(p, t, kMaxWaves, lds_);
+      step3_tile<S, A, KA, NG, PER, true>(p, t, blockDim.x >> 6, lds_);
     __threadfence();
     __syncthreads();
   }
