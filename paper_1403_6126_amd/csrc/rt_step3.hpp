@@ -254,13 +254,18 @@ __device__ __forceinline__ void stream_store(T *p, T v) {
 #ifndef RT_IC_REG_F32
 #define RT_IC_REG_F32 1
 #endif
-// Slots whose plane reads are in flight ahead of the transport arithmetic
-// (FP64 storage: one, as registers allow).
+// Slots whose plane reads are in flight ahead of the transport arithmetic:
+// six in both precisions (FP64 3.89 -> 3.67 ms and FP32 1.88 -> 1.82 ms on
+// the 128^3 S8 box against the earlier two and three; FP64 at 255 VGPRs).
 #ifndef RT_PREFETCH_F64
-#define RT_PREFETCH_F64 2
+#define RT_PREFETCH_F64 6
+#endif
+// (FP64 with three or four groups per wave: two, as its registers allow)
+#ifndef RT_PREFETCH_F64_WIDE
+#define RT_PREFETCH_F64_WIDE 2
 #endif
 #ifndef RT_PREFETCH_F32
-#define RT_PREFETCH_F32 3
+#define RT_PREFETCH_F32 6
 #endif
 
 // Entry i of an angle table in the arithmetic type: the FP32 copy (equal to
@@ -282,11 +287,67 @@ __device__ __forceinline__ const A *angle_rec(const StepArgs &p, int m) {
     return p.arec + (size_t)m * kRec;
 }
 
-// LDS of one step body, for G waves (dynamic shared memory of the launch):
-// the cross-wave reduction rows (G*kChunk*64 doubles), the reduced values
-// (kChunk*64) and the solution passed on by wave 0 (6*64).
-__host__ __device__ constexpr size_t step3_lds_bytes(int G) {
-  return sizeof(double) * ((size_t)G * kChunk * 64 + kChunk * 64 + 6 * 64);
+// The axis data of a tile in LDS during the transport (the same bytes hold
+// the reductions afterwards): per axis 8 words of cell indices and ghost
+// kinds and 20 values of the arithmetic type, each a row of 64 lanes.
+constexpr int kAxisWords = 8, kAxisVals = 20;
+__host__ __device__ constexpr size_t axis_lds_bytes(int abytes) {
+  return (size_t)3 * 64 * (kAxisWords * 4 + kAxisVals * (size_t)abytes);
+}
+
+// LDS of one step body, for G waves and abytes-byte arithmetic (dynamic
+// shared memory of the launch): the cross-wave reduction rows
+// (G*kChunk*64 doubles), the reduced values (kChunk*64) and the solution
+// passed on by wave 0 (6*64), or the axis data of the transport if larger.
+__host__ __device__ constexpr size_t step3_lds_bytes(int G, int abytes) {
+  const size_t red = sizeof(double) * ((size_t)G * kChunk * 64 + kChunk * 64 + 6 * 64);
+  const size_t ax = axis_lds_bytes(abytes);
+  return red > ax ? red : ax;
+}
+
+// Axis d's data of the tile: stored by the wave that built it, read by every
+// wave (lane by lane, so the 64 lanes hit 64 consecutive words).
+template <typename A>
+__device__ __forceinline__ void axis_put(double *lds, int d, const AxisData<A> &s, int lane) {
+  char *base = reinterpret_cast<char *>(lds) + (size_t)d * 64 * (kAxisWords * 4 + kAxisVals * sizeof(A));
+  int *w = reinterpret_cast<int *>(base);
+  A *v = reinterpret_cast<A *>(base + 64 * kAxisWords * 4);
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    w[j * 64 + lane] = (int)s.idx[j];
+    w[(4 + j) * 64 + lane] = s.kind[j];
+  }
+#pragma unroll
+  for (int j = 0; j < 4; ++j)
+#pragma unroll
+    for (int t = 0; t < 3; ++t) v[(j * 3 + t) * 64 + lane] = s.dW[j][t];
+  const A co[8] = {s.caL, s.cbL, s.caR, s.cbR, s.lL, s.rR, s.fL, s.fR};
+#pragma unroll
+  for (int j = 0; j < 8; ++j) v[(12 + j) * 64 + lane] = co[j];
+}
+template <typename A, bool PER>
+__device__ __forceinline__ void axis_get(const double *lds, int d, AxisData<A> &s, int lane) {
+  const char *base =
+      reinterpret_cast<const char *>(lds) + (size_t)d * 64 * (kAxisWords * 4 + kAxisVals * sizeof(A));
+  const int *w = reinterpret_cast<const int *>(base);
+  const A *v = reinterpret_cast<const A *>(base + 64 * kAxisWords * 4);
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    s.idx[j] = (unsigned)w[j * 64 + lane];
+    s.kind[j] = PER ? 0 : w[(4 + j) * 64 + lane];
+  }
+#pragma unroll
+  for (int j = 0; j < 4; ++j)
+#pragma unroll
+    for (int t = 0; t < 3; ++t) s.dW[j][t] = v[(j * 3 + t) * 64 + lane];
+  s.caL = v[12 * 64 + lane];
+  s.cbL = v[13 * 64 + lane];
+  s.caR = v[14 * 64 + lane];
+  s.cbR = v[15 * 64 + lane];
+  s.lL = v[16 * 64 + lane];
+  s.rR = v[17 * 64 + lane];
+  s.fL = v[18 * 64 + lane];
+  s.fR = v[19 * 64 + lane];
 }
 
 // The reduced absorption system of one cell (Section 4.3, Eq.
@@ -402,22 +463,31 @@ __device__ __forceinline__ void step3_tile(const StepArgs &p, int blk, int G, do
   }
   if (FUSED) {
     const int q[3] = {c % p.n[0], (c / p.n[0]) % p.n[1], c / (p.n[0] * p.n[1])};
-    const A Wc[3] = {A(p.mom_in[10 * N + c]), A(p.mom_in[11 * N + c]), A(p.mom_in[12 * N + c])};
     const A invC = A(p.invC);
+    // the axis data of the tile, each axis built by one wave (wave g takes
+    // axes g, g + G, ...) and shared through LDS
+    {
+      const A Wc[3] = {A(p.mom_in[10 * N + c]), A(p.mom_in[11 * N + c]),
+                       A(p.mom_in[12 * N + c])};
+      for (int d = g; d < p.ndim; d += G) {
+        AxisData<A> s;
+        load_axis<A, PER>(p, c, q, d, Wc, s);
+        axis_put(lds, d, s, lane);
+      }
+    }
+    __syncthreads();
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
       if (d >= p.ndim) break;
       if (CELL_EARLY && d == p.ndim - 1) cell_load();
       AxisData<A> s;
-      load_axis<A, PER>(p, c, q, d, Wc, s);
+      axis_get<A, PER>(lds, d, s, lane);
       constexpr int UNR = sizeof(A) == 8 ? RT_UNROLL_F64 : RT_UNROLL_F32;
       // the plane reads of a slot: cells -1 and +1 and the far upwind cell
-      // (-2 for mu_d > 0, else +2).  Those of the PF next slots are issued
-      // before the arithmetic of the current one, so that their latency
-      // overlaps it.
-      // (padding slots read the last plane: their zero records make every
-      // term they contribute zero, and the loads stay unconditional so that
-      // the waits for them can be counted precisely)
+      // (-2 for mu_d > 0, else +2).  Those of the PF next slots of the axis
+      // are issued before the arithmetic of the current one, so that their
+      // latency overlaps it.  (Carrying the ring across the end of an axis
+      // into the next one measured slower.)
       auto reads = [&](int k, S (&r)[4]) {
         if (RT_UNCOND_LOADS || slot_m(k) < NA) {
           const S *Im = slot_m(k) < NA ? slot_plane(k) : Iin + (size_t)(NA - 1) * N;
@@ -437,11 +507,13 @@ __device__ __forceinline__ void step3_tile(const StepArgs &p, int blk, int G, do
           r[0] = r[1] = r[2] = r[3] = S(0);
         }
       };
-      constexpr int PF = sizeof(A) == 8 ? RT_PREFETCH_F64 : RT_PREFETCH_F32;
+      constexpr int PF0 = sizeof(A) == 4 ? RT_PREFETCH_F32
+                          : NG <= 2     ? RT_PREFETCH_F64
+                                        : RT_PREFETCH_F64_WIDE;
+      constexpr int PF = PF0 < NS ? PF0 : NS;
       S rq[PF][4];
 #pragma unroll
-      for (int j = 0; j < PF; ++j)
-        if (j < NS) reads(j, rq[j]);
+      for (int j = 0; j < PF; ++j) reads(j, rq[j]);
 #pragma unroll UNR
       for (int k = 0; k < NS; ++k) {
         S r[4];
@@ -488,6 +560,7 @@ __device__ __forceinline__ void step3_tile(const StepArgs &p, int blk, int G, do
         }
       }
     }
+    __syncthreads();  // the reductions below reuse the LDS of the axis data
   } else {
     const S *dFin = static_cast<const S *>(p.dF_in);
     if (dFin) {
@@ -875,8 +948,8 @@ k_step3(StepArgs p) {
 // A whole solve per workgroup: job blockIdx.x advances its grid through
 // nsteps fused steps, tile by tile (64 cells per tile, the waves of the
 // context's launch shape, the same step body as k_step3, hence the same
-// per-cell results and partial totals), and reduces the partial totals after the last step like
-// k_totals.  Between steps the workgroup fences its global writes (I,
+// per-cell results and partial totals), and reduces the partial totals
+// after the last step like k_totals.  Between steps the workgroup fences its global writes (I,
 // moments, T, partials) before any wave reads them.
 template <typename S, typename A, int KA, int NG, bool PER>
 __global__ __launch_bounds__(64 * kMaxWaves) void k_step3_packed(
@@ -899,8 +972,12 @@ __global__ __launch_bounds__(64 * kMaxWaves) void k_step3_packed(
     p.oE = last ? oE : nullptr;
     p.oF = last ? oF : nullptr;
     p.oP = last ? oP : nullptr;
-    for (int t = 0; t < ntiles; ++t)
+    for (int t = 0; t < ntiles; ++t) {
+      // the tile body's first LDS writes (the axis data) may overlap the
+      // reduced values the previous tile's waves are still reading
+      if (t > 0) __syncthreads();
       step3_tile<S, A, KA, NG, PER, true>(p, t, blockDim.x >> 6, lds_);
+    }
     __threadfence();
     __syncthreads();
   }
