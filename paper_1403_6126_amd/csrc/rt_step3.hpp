@@ -243,6 +243,12 @@ __device__ __forceinline__ void stream_store(T *p, T v) {
 #ifndef RT_UNCOND_LOADS
 #define RT_UNCOND_LOADS 0
 #endif
+// A scheduling fence at the start of every slot of the transport keeps the
+// plane reads where the prefetch ring puts them (FP64 3.69 -> 3.61 ms,
+// FP32 1.81 -> 1.79 ms with eight slots ahead, and fewer registers).
+#ifndef RT_SLOT_FENCE
+#define RT_SLOT_FENCE 1
+#endif
 #ifndef RT_BUFFER_LOADS
 #define RT_BUFFER_LOADS 1
 #endif
@@ -255,17 +261,18 @@ __device__ __forceinline__ void stream_store(T *p, T v) {
 #define RT_IC_REG_F32 1
 #endif
 // Slots whose plane reads are in flight ahead of the transport arithmetic:
-// six in both precisions (FP64 3.89 -> 3.67 ms and FP32 1.88 -> 1.82 ms on
-// the 128^3 S8 box against the earlier two and three; FP64 at 255 VGPRs).
+// eight in both precisions (six against two and three: FP64 3.89 -> 3.67
+// ms and FP32 1.88 -> 1.82 ms on the 128^3 S8 box; eight with the slot
+// fence a further 1-2 %; FP64 at 237 VGPRs).
 #ifndef RT_PREFETCH_F64
-#define RT_PREFETCH_F64 6
+#define RT_PREFETCH_F64 8
 #endif
 // (FP64 with three or four groups per wave: two, as its registers allow)
 #ifndef RT_PREFETCH_F64_WIDE
 #define RT_PREFETCH_F64_WIDE 2
 #endif
 #ifndef RT_PREFETCH_F32
-#define RT_PREFETCH_F32 6
+#define RT_PREFETCH_F32 8
 #endif
 
 // Entry i of an angle table in the arithmetic type: the FP32 copy (equal to
@@ -278,13 +285,29 @@ __device__ __forceinline__ A tab(const double *d, const float *f, int i) {
     return d[i];
 }
 
+// A pointer into the constant address space: the angle records are read-only
+// for the whole step, and reads through such a pointer at a wave-uniform
+// address become scalar loads even after the step's global writes and
+// atomics (through a generic pointer the compiler makes vector loads of
+// them there).  128^3 S8: FP64 3.56 -> 3.18 ms, FP32 1.79 -> 1.58 ms.
+#ifndef RT_CONST_RECORDS
+#define RT_CONST_RECORDS 1
+#endif
+#if RT_CONST_RECORDS
+template <typename T>
+using cptr = const __attribute__((address_space(4))) T *;
+#else
+template <typename T>
+using cptr = const T *;
+#endif
+
 // The record of angle m (StepArgs::arec) in the arithmetic type.
 template <typename A>
-__device__ __forceinline__ const A *angle_rec(const StepArgs &p, int m) {
+__device__ __forceinline__ cptr<A> angle_rec(const StepArgs &p, int m) {
   if constexpr (sizeof(A) == 4)
-    return p.arecf + (size_t)m * kRec;
+    return (cptr<A>)(p.arecf + (size_t)m * kRec);
   else
-    return p.arec + (size_t)m * kRec;
+    return (cptr<A>)(p.arec + (size_t)m * kRec);
 }
 
 // The axis data of a tile in LDS during the transport (the same bytes hold
@@ -412,8 +435,8 @@ __device__ __forceinline__ void step3_tile(const StepArgs &p, int blk, int G, do
   const int m0 = g * KA;
   auto slot_off = [&](int s) { return (s / KA) * G * KA + (s % KA); };
   auto slot_m = [&](int s) { return m0 + slot_off(s); };
-  const A *Rg = angle_rec<A>(p, m0);
-  const double *Rgd = p.arec + (size_t)m0 * kRec;
+  const cptr<A> Rg = angle_rec<A>(p, m0);
+  const cptr<double> Rgd = (cptr<double>)(p.arec + (size_t)m0 * kRec);
   const S *Ig = Iin + (size_t)m0 * N;
   S *Og = Iout + (size_t)m0 * N;
   auto slot_rec = [&](int s) { return Rg + (unsigned)slot_off(s) * kRec; };
@@ -516,6 +539,7 @@ __device__ __forceinline__ void step3_tile(const StepArgs &p, int blk, int G, do
       for (int j = 0; j < PF; ++j) reads(j, rq[j]);
 #pragma unroll UNR
       for (int k = 0; k < NS; ++k) {
+        if constexpr (RT_SLOT_FENCE) __builtin_amdgcn_sched_barrier(0);
         S r[4];
 #pragma unroll
         for (int t = 0; t < 4; ++t) r[t] = rq[0][t];
@@ -526,7 +550,7 @@ __device__ __forceinline__ void step3_tile(const StepArgs &p, int blk, int G, do
         if (k + PF < NS) reads(k + PF, rq[PF - 1]);
         const int m = slot_m(k);
         const int mc = m < NA ? m : NA - 1;
-        const A *R = slot_rec(k);  // padding slots: zero records
+        const cptr<A> R = slot_rec(k);  // padding slots: zero records
         const A mud = R[rec_n0 + d];
         if (RT_UNCOND_LOADS || (m < NA && mud != A(0))) {  // uniform over the wave
           const A n0 = R[rec_n0], n1 = R[rec_n1], n2 = R[rec_n2];
@@ -621,7 +645,7 @@ __device__ __forceinline__ void step3_tile(const StepArgs &p, int blk, int G, do
 #pragma unroll
     for (int k = 0; k < NS; ++k) {
       if (slot_m(k) >= NA) continue;
-      const A *R = slot_rec(k);
+      const cptr<A> R = slot_rec(k);
       const A n0 = R[rec_n0], n1 = R[rec_n1], n2 = R[rec_n2];
       const A t = n0 * Au0 + n1 * Au1 + n2 * Au2;
       const A invD = fast_rcp(D0 - dsa * t);
@@ -679,7 +703,7 @@ __device__ __forceinline__ void step3_tile(const StepArgs &p, int blk, int G, do
     pk[k] = A(0);
     const int m = slot_m(k);
     if (m >= NA) continue;
-    const A *R = slot_rec(k);
+    const cptr<A> R = slot_rec(k);
     const A n0 = R[rec_n0], n1 = R[rec_n1], n2 = R[rec_n2];
     const A Wm = R[rec_w];
     const A t = n0 * Au0 + n1 * Au1 + n2 * Au2;  // scattering: at u
@@ -793,7 +817,7 @@ __device__ __forceinline__ void step3_tile(const StepArgs &p, int blk, int G, do
   for (int k = 0; k < NS; ++k) {
     const int m = slot_m(k);
     if (m >= NA) continue;
-    const A *R = slot_rec(k);
+    const cptr<A> R = slot_rec(k);
     const A t = R[rec_n0] * Au0 + R[rec_n1] * Au1 + R[rec_n2] * Au2;
     const A ta = SO ? R[rec_n0] * Ua0 + R[rec_n1] * Ua1 + R[rec_n2] * Ua2 : t;
     const A D = D0 - dsa * ta, aw = AW0 - dss * t;
