@@ -48,7 +48,8 @@ VALU_ISSUE_PEAK = 256 * 4 * 16 * 2.4e9
 #     the new intensity (6), the 10 moments (10): 61.
 ALG_OPS_PER_CELL_ANGLE_3D = 128
 STEP_SOURCES = ("rt_step3.hpp", "rt_common.hpp", "rt_internal.hpp", "rt_kernels.inc",
-                "rt_kernels_f64.hip", "rt_kernels_f32.hip")
+                "rt_kernels_f64.hip", "rt_kernels_f32.hip", "rt_step3_inst.inc") + tuple(
+                    f"rt_step3_{p}_g{g}.hip" for p in ("f64", "f32") for g in (1, 2, 3, 4))
 
 
 def algorithmic_bytes_per_cell(nang: int, sbytes: int) -> int:

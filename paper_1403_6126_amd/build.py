@@ -13,8 +13,11 @@ from concurrent.futures import ThreadPoolExecutor
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
-SOURCES = ("rt_kernels_f64.hip", "rt_kernels_f32.hip", "rt_api.hip", "rt_serve.hip",
-           "rt_quadrature.cpp")
+# the wave-group step kernels, one unit per precision and groups per wave
+# (the largest first, so that the pool overlaps them), then the rest
+SOURCES = tuple(f"rt_step3_{p}_g{g}.hip" for g in (4, 3, 2, 1) for p in ("f32", "f64")) + (
+    "rt_kernels_f64.hip", "rt_kernels_f32.hip", "rt_api.hip", "rt_serve.hip",
+    "rt_quadrature.cpp")
 LIB = os.path.join(HERE, "librt.so")
 OBJDIR = os.path.join(HERE, "_build")
 
@@ -26,13 +29,10 @@ HIPCC_FLAGS = [
 ]
 
 
-# Per-file additions: the FP64 step kernels schedule with the iterative
-# occupancy-preserving strategy of the AMDGPU backend, which measured about
-# 2 % faster on the FP64 fused step (latency-bound at four waves per SIMD);
-# the FP32 kernels keep the default.
-EXTRA_FLAGS = {
-    "rt_kernels_f64.hip": ["-mllvm", "-amdgpu-sched-strategy=iterative-maxocc"],
-}
+# Per-file additions (none at present: the backend's iterative
+# occupancy-preserving scheduler, once 2 % faster for the FP64 step at four
+# waves per SIMD, no longer gains at two and doubles the build time).
+EXTRA_FLAGS: dict = {}
 
 
 def _hipcc() -> str:

@@ -41,6 +41,24 @@ hipError_t launch_step_f64(const StepArgs &a, const KShape &k, bool fused, long 
                            hipStream_t s);
 hipError_t launch_step_f32(const StepArgs &a, const KShape &k, bool fused, long long blocks,
                            hipStream_t s);
+// The wave-group kernels of one precision and number of groups per wave
+// (rt_step3_<f64|f32>_g<1..4>.hip): fused, second-order fused (k.second) or
+// source-only steps, and (FP32) the packed persistent launches.
+#define RT_DECLARE_STEP3(suf, ng)                                                           \
+  void launch_step3_##suf##_##ng(const StepArgs &a, const KShape &k, bool fused,            \
+                                 long long blocks, hipStream_t s);                          \
+  void launch_packed_##suf##_##ng(const PackedJob *jobs, int njobs, int waves, bool periodic, \
+                                  hipStream_t s);
+RT_DECLARE_STEP3(f64, 1)
+RT_DECLARE_STEP3(f64, 2)
+RT_DECLARE_STEP3(f64, 3)
+RT_DECLARE_STEP3(f64, 4)
+RT_DECLARE_STEP3(f32, 1)
+RT_DECLARE_STEP3(f32, 2)
+RT_DECLARE_STEP3(f32, 3)
+RT_DECLARE_STEP3(f32, 4)
+#undef RT_DECLARE_STEP3
+
 // Packed persistent launches: one workgroup of 64*waves threads per job;
 // every job of a launch has the launch shape (waves, groups) of its own
 // context, so that it sums its angles in the order rt_step does, and the

@@ -225,9 +225,13 @@ __device__ __forceinline__ void stream_store(T *p, T v) {
 }
 
 // The temperature and scattering solve on every wave (1) or on wave 0 with
-// the solution passed through LDS (0).
-#ifndef RT_SOLVE_ALL
-#define RT_SOLVE_ALL 1
+// the solution passed through LDS (0): FP64 on wave 0 measured 1 % faster,
+// FP32 the same either way.
+#ifndef RT_SOLVE_ALL_F64
+#define RT_SOLVE_ALL_F64 0
+#endif
+#ifndef RT_SOLVE_ALL_F32
+#define RT_SOLVE_ALL_F32 1
 #endif
 // Per-cell fields loaded before the last axis of the transport (1) or after
 // the transport (0).
@@ -756,10 +760,11 @@ __device__ __forceinline__ void step3_tile(const StepArgs &p, int blk, int G, do
 
   // --------------------------------------------- solve (FP64)
   // Every wave holds the reduced sums of its 64 cells, so every wave can
-  // solve them (RT_SOLVE_ALL, no barrier and no idle waves), or wave 0
+  // solve them (SOLVE_ALL, no barrier and no idle waves), or wave 0
   // solves and passes the solution on through LDS.
   double X = 0.0, kQ = 0.0, s1 = 0.0, s2 = 0.0, T = 0.0, newton_it = 0.0;
-  if (RT_SOLVE_ALL || g == 0) {
+  constexpr bool SOLVE_ALL = sizeof(A) == 8 ? RT_SOLVE_ALL_F64 : RT_SOLVE_ALL_F32;
+  if (SOLVE_ALL || g == 0) {
     double Q;
     int it;
     bool conv;
@@ -779,7 +784,7 @@ __device__ __forceinline__ void step3_tile(const StepArgs &p, int blk, int G, do
     s2 = (a11 * Sr5 - a21 * Sbr) * idet;
     newton_it = double(it);
   }
-  if constexpr (!RT_SOLVE_ALL) {
+  if constexpr (!SOLVE_ALL) {
     if (g == 0) {
       ssol[0 * 64 + lane] = X;
       ssol[1 * 64 + lane] = kQ;
