@@ -234,9 +234,10 @@ __device__ __forceinline__ void stream_store(T *p, T v) {
 #define RT_SOLVE_ALL_F32 1
 #endif
 // Per-cell fields loaded before the last axis of the transport (1) or after
-// the transport (0).
+// the transport (0: fewer registers live in the transport, which lets FP64
+// run three waves per SIMD).
 #ifndef RT_CELL_EARLY_F64
-#define RT_CELL_EARLY_F64 1
+#define RT_CELL_EARLY_F64 0
 #endif
 #ifndef RT_CELL_EARLY_F32
 #define RT_CELL_EARLY_F32 0
@@ -257,19 +258,24 @@ __device__ __forceinline__ void stream_store(T *p, T v) {
 #define RT_BUFFER_LOADS 1
 #endif
 // The cell's intensities held in registers over the transport (1) or read
-// again per slot (0: measured 8 % slower in FP64, 4 % in FP32).
+// again per slot (0, from L1: the center cell shares its lines with the
+// neighbour reads).  FP64 reads them again, which with the per-cell fields
+// after the transport fits three waves per SIMD in 168 VGPRs (3.17 -> 2.76
+// ms on the 128^3 S8 box); FP32 keeps them (4 % slower reading again at
+// four waves).
 #ifndef RT_IC_REG_F64
-#define RT_IC_REG_F64 1
+#define RT_IC_REG_F64 0
 #endif
 #ifndef RT_IC_REG_F32
 #define RT_IC_REG_F32 1
 #endif
 // Slots whose plane reads are in flight ahead of the transport arithmetic:
-// eight in both precisions (six against two and three: FP64 3.89 -> 3.67
-// ms and FP32 1.88 -> 1.82 ms on the 128^3 S8 box; eight with the slot
-// fence a further 1-2 %; FP64 at 237 VGPRs).
+// FP32 eight (six against three: 1.88 -> 1.82 ms on the 128^3 S8 box,
+// eight with the slot fence a further 1 %); FP64 five, the most that three
+// waves per SIMD hold without spilling (2.80 ms at three and four, 2.76 at
+// five).
 #ifndef RT_PREFETCH_F64
-#define RT_PREFETCH_F64 8
+#define RT_PREFETCH_F64 5
 #endif
 // (FP64 with three or four groups per wave: two, as its registers allow)
 #ifndef RT_PREFETCH_F64_WIDE
@@ -943,12 +949,13 @@ __device__ __forceinline__ void step3_tile(const StepArgs &p, int blk, int G, do
   }
 }
 
-// Waves per SIMD the register allocation of k_step3 targets.  FP64 at 2
-// (256 VGPRs, no spill; with 4-wave blocks two blocks share a CU) measured
-// 3.9 ms on the 128^3 S8 box against 4.6-4.8 ms at 4 (128 VGPRs with a
-// 170-byte spill whose traffic dominated); FP32 at 4 does not spill.
+// Waves per SIMD the register allocation of k_step3 targets.  FP64 at 3
+// (168 VGPRs: the cell's intensities read again per slot and the per-cell
+// fields after the transport; with 4-wave blocks three blocks share a CU)
+// against 2 (256 VGPRs): 2.76 against 3.17 ms on the 128^3 S8 box; at 4
+// it spills.  FP32 at 4 does not spill (at 5 it does).
 #ifndef RT_STEP3_WAVES_F64
-#define RT_STEP3_WAVES_F64 2
+#define RT_STEP3_WAVES_F64 3
 #endif
 #ifndef RT_STEP3_WAVES_F32
 #define RT_STEP3_WAVES_F32 4
