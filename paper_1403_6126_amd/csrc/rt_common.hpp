@@ -159,13 +159,20 @@ __device__ __forceinline__ int xcd_block(int b, int nb) {
 // neighbours along y and z) run on the same XCD within a few tens of blocks
 // of it.  Grids whose planes do not hold whole tiles, or with fewer than 8
 // planes, take the XCD-contiguous order.
-__device__ __forceinline__ int slab_block(int b, int nb, const int (&n)[3]) {
+// With sub > 0 (dividing the slab depth) the slab is worked through in
+// sub-slabs of sub planes, so that the tiles beside a tile along y are nearer
+// in time, at the price of the z-neighbours across sub-slab boundaries.
+__device__ __forceinline__ int slab_block(int b, int nb, const int (&n)[3], int sub = 0) {
   const int plane = n[0] * n[1];
   if (n[2] < 8 || (n[2] & 7) || (plane & 63)) return xcd_block(b, nb);
   const int pt = plane >> 6;           // tiles per z-plane
   const int zc = n[2] >> 3;            // z-planes per XCD slab
   const int pos = (b & 7) * (nb >> 3) + (b >> 3);
   const int slab = pos / (zc * pt), r = pos - slab * (zc * pt);
+  if (sub > 0 && sub < zc && zc % sub == 0) {
+    const int ss = r / (sub * pt), r2 = r - ss * (sub * pt);
+    return (slab * zc + ss * sub + r2 % sub) * pt + r2 / sub;
+  }
   const int z = slab * zc + r % zc;
   return z * pt + r / zc;
 }
