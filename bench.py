@@ -98,7 +98,8 @@ def kernel_name(info, storage_bytes: int) -> str:
     ng = -(-info["nang"] // 10)
     groups = -(-ng // waves)
     per = "true" if info.get("periodic", True) else "false"
-    return f"rtk::k_step3<{t}, {t}, 10, {groups}, {per}, true>"
+    so = "true" if info.get("second_order", False) else "false"
+    return f"rtk::k_step3<{t}, {t}, 10, {groups}, {per}, true, {so}>"
 
 
 def rooflines(r, tag: str, wname: str):
