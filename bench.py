@@ -331,7 +331,7 @@ def main():
                     help="profiling: run one precision only and print its timing")
     ap.add_argument("--second-order", action="store_true",
                     help="with --only: time the step with the absorption system solved twice "
-                         "(the thread-per-cell kernel)")
+                         "(second-order absorption)")
     ap.add_argument("--serve-requests", type=int, default=200,
                     help="requests of the serving trace (0: skip; 2000 = the full stream)")
     ap.add_argument("--serve-load", type=float, nargs="+", default=[0.8, 1.2],
