@@ -108,6 +108,9 @@ CASES = [
     (3, (12, 10, 9), ("ls", 4), ((W.BC_FIXED, W.BC_FIXED), (W.BC_COPY, W.BC_VACUUM),
                                  (W.BC_PERIODIC, W.BC_PERIODIC))),
     (1, (129,), ("gl", 32), ((W.BC_VACUUM, W.BC_COPY), (0, 0), (0, 0))),
+    # eight directions: one wave builds the stencil data of all three axes
+    (3, (10, 9, 7), ("ls", 2), None),
+    (2, (21, 17), ("ls", 2), ((W.BC_FIXED, W.BC_VACUUM), (W.BC_COPY, W.BC_VACUUM), (0, 0))),
     # more than 80 directions: 2, 3 and 4 angle groups per wave
     (3, (9, 8, 7), ("ls", 10), None),
     (2, (13, 11), ("ls", 12), ((W.BC_FIXED, W.BC_VACUUM), (W.BC_COPY, W.BC_FIXED), (0, 0))),
