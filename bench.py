@@ -57,16 +57,25 @@ def algorithmic_bytes_per_cell(nang: int, sbytes: int) -> int:
     return 2 * sbytes * nang + FIELD_BYTES_PER_CELL
 
 
+def _code_only(text: str) -> str:
+    """C++ source without its comments and blank lines (string literals in
+    these files hold no comment markers)."""
+    import re
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    text = re.sub(r"//[^\n]*", "", text)
+    return "\n".join(line.rstrip() for line in text.splitlines() if line.strip())
+
+
 def kernel_source_sha() -> str:
-    """Digest of the fused step kernel's sources and build flags: counters
-    taken on another kernel do not describe this one."""
+    """Digest of the fused step kernel's code (comments aside) and build
+    flags: counters taken on another kernel do not describe this one."""
     import hashlib
 
     from paper_1403_6126_amd import build as B
     h = hashlib.sha256()
     for name in STEP_SOURCES:
-        with open(os.path.join(B.CSRC, name), "rb") as f:
-            h.update(f.read())
+        with open(os.path.join(B.CSRC, name), encoding="utf-8") as f:
+            h.update(_code_only(f.read()).encode())
     h.update(" ".join(B.HIPCC_FLAGS).encode())
     h.update(json.dumps(B.EXTRA_FLAGS, sort_keys=True).encode())
     return h.hexdigest()[:16]

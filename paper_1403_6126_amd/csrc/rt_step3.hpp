@@ -7,17 +7,21 @@
 // uniform, so the direction cosines, weights and the upwind
 // direction of every axis are scalars, and every intensity load reads 64
 // consecutive cells of one angle plane.  Per step:
+//   axes     the stencil data of each active axis (cell indices, ghost
+//            kinds, 3vJ differences, face coefficients) built by one wave
+//            and shared with the others through LDS;
 //   phase A  transport increment of the wave's angles (Section 4.2), one
 //            active axis at a time: the flux difference of the two faces
 //            from the differences of I~ and IV between consecutive stencil
 //            cells, with a per-call interface table (C alpha, IV upwinding)
-//            and per-angle factors (mu_d dt/dx, 1 - nu) read as scalars;
+//            and per-angle records (mu_d, 1 - nu, weights) read as scalars;
 //   phase B  the absorption right-hand side r4 and the wave's partial sums of
 //            the per-cell sums of the reduced absorption and scattering
 //            systems; the per-angle values stay in registers;
 //   reduce   the partial sums across the waves (LDS, fixed order);
-//   solve    wave 0: FP64 Newton on the quartic in T' and the 2 x 2
-//            scattering system; the solution goes to the other waves via LDS;
+//   solve    FP64 Newton on the quartic in T' and the 2 x 2 scattering
+//            system, on every wave or on wave 0 with the solution passed on
+//            through LDS;
 //   phase C  I^{n+1} of the wave's angles, written once, and the partial
 //            moments, reduced across the waves like the sums.
 #pragma once
