@@ -58,12 +58,12 @@ def algorithmic_bytes_per_cell(nang: int, sbytes: int) -> int:
 
 
 def _code_only(text: str) -> str:
-    """C++ source without its comments and blank lines (string literals in
-    these files hold no comment markers)."""
+    """C++ source without its comments, blank lines and indentation (string
+    literals in these files hold no comment markers)."""
     import re
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
     text = re.sub(r"//[^\n]*", "", text)
-    return "\n".join(line.rstrip() for line in text.splitlines() if line.strip())
+    return "\n".join(line.strip() for line in text.splitlines() if line.strip())
 
 
 def kernel_source_sha() -> str:
