@@ -86,8 +86,9 @@ enum { RT_QUAD_GAUSS_LEGENDRE = 0, RT_QUAD_LEVEL_SYMMETRIC = 1 };
  * change d4 of that solution gives the time-centred velocity
  * v + d4/(2 rho), and the system is solved again at that velocity from the
  * same right-hand side and T^n; the second solution is the step's.  The
- * scattering step keeps u.  Runs on the thread-per-cell step kernel (about
- * twice the source-step work); RT_EUNSUPPORTED with RT_GAS_FEEDBACK. */
+ * scattering step keeps u.  rt_step runs both solves in its fused kernel
+ * (about 1.2 times the single-solve step); rt_source_implicit runs the step
+ * per cell.  RT_EUNSUPPORTED with RT_GAS_FEEDBACK. */
 #define RT_SECOND_ORDER 8u
 /* Number of entries of the totals vector. */
 #define RT_NTOT 12
