@@ -27,7 +27,8 @@ namespace rtk {
 //   j = 2  the signed van Leer factor of the IV value, sign(u) (1 - nu_v),
 //          nu_v = |u| dt/dx (0 at u = 0).
 // arec[m*kRec + f] (FP64, and FP32 copies) are the per-angle records of the
-// call: direction, 1 - C |mu_d| dt/dx_d, w, w n_d and w n_i n_j; records
+// call: direction, 1 - C |mu_d| dt/dx_d, w, w n_d, w n_i n_j and the sign
+// bits of the direction (as integers in the slot's low word); records
 // nang .. nrec-1 (the padding slots of the wave-group kernel) are zero.
 // wv = 3 v E/(4pi) of the current moments into mom[10..12].  One thread per
 // cell and per record (max of the two).
@@ -53,9 +54,22 @@ __global__ __launch_bounds__(kBlock) void k_faces(StepArgs p, double *faces, dou
       r[rec_wnn + 4] = w * n[0] * n[2];
       r[rec_wnn + 5] = w * n[1] * n[2];
     }
+    // the signs of the direction as integer bits (the step kernel tests
+    // them on the scalar unit, which has no floating-point compare)
+    unsigned flags = 0;
+    for (int d = 0; d < 3; ++d) {
+      if (r[rec_n0 + d] > 0.0) flags |= 1u << d;
+      if (r[rec_n0 + d] != 0.0) flags |= 8u << d;
+    }
     for (int f = 0; f < kRec; ++f) {
-      arec[(size_t)c * kRec + f] = r[f];
-      arecf[(size_t)c * kRec + f] = float(r[f]);
+      if (f == rec_flags) {
+        unsigned long long bits = flags;
+        arec[(size_t)c * kRec + f] = __longlong_as_double((long long)bits);
+        arecf[(size_t)c * kRec + f] = __uint_as_float(flags);
+      } else {
+        arec[(size_t)c * kRec + f] = r[f];
+        arecf[(size_t)c * kRec + f] = float(r[f]);
+      }
     }
   }
   if (c >= p.ncell) return;

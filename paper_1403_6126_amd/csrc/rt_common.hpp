@@ -24,7 +24,8 @@ enum RecField : int {
   rec_w,                        // weight
   rec_wn0, rec_wn1, rec_wn2,    // w n_d
   rec_wnn,                      // 6 values: w n_x n_x, w n_y n_y, w n_z n_z, w n_x n_y, w n_x n_z, w n_y n_z
-  kRec = 16
+  rec_flags = rec_wnn + 6,      // integer bits in the slot: bit d n_d > 0, bit 3 + d n_d != 0
+  kRec = 17
 };
 
 // Arguments of every step kernel (passed by value).

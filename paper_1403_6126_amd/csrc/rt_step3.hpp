@@ -454,6 +454,10 @@ __device__ __forceinline__ void step3_tile(const StepArgs &p, int blk, int G, do
   const S *Ig = Iin + (size_t)m0 * N;
   S *Og = Iout + (size_t)m0 * N;
   auto slot_rec = [&](int s) { return Rg + (unsigned)slot_off(s) * kRec; };
+  // the sign bits of a slot's direction (scalar integer tests)
+  auto slot_flags = [&](int s) -> unsigned {
+    return ((cptr<unsigned>)(Rg + (unsigned)slot_off(s) * kRec + rec_flags))[0];
+  };
   auto slot_plane = [&](int s) { return Ig + (size_t)(unsigned)slot_off(s) * N; };
 
   // The cell's fields and the moments of I^n used by the velocity estimate.
@@ -528,7 +532,7 @@ __device__ __forceinline__ void step3_tile(const StepArgs &p, int blk, int G, do
       auto reads = [&](int k, S (&r)[4]) {
         if (RT_UNCOND_LOADS || slot_m(k) < NA) {
           const S *Im = slot_m(k) < NA ? slot_plane(k) : Iin + (size_t)(NA - 1) * N;
-          const unsigned far = slot_rec(k)[rec_n0 + d] > A(0) ? s.idx[0] : s.idx[3];
+          const unsigned far = (slot_flags(k) >> d) & 1u ? s.idx[0] : s.idx[3];
           if constexpr (RT_BUFFER_LOADS) {
             r[0] = plane_buf_ld(Im, s.idx[1]);
             r[1] = plane_buf_ld(Im, s.idx[2]);
@@ -566,7 +570,8 @@ __device__ __forceinline__ void step3_tile(const StepArgs &p, int blk, int G, do
         const int mc = m < NA ? m : NA - 1;
         const cptr<A> R = slot_rec(k);  // padding slots: zero records
         const A mud = R[rec_n0 + d];
-        if (RT_UNCOND_LOADS || (m < NA && mud != A(0))) {  // uniform over the wave
+        const unsigned fl = slot_flags(k);
+        if (RT_UNCOND_LOADS || (m < NA && ((fl >> (3 + d)) & 1u))) {  // mu_d != 0, uniform
           const A n0 = R[rec_n0], n1 = R[rec_n1], n2 = R[rec_n2];
           const A h2 = R[rec_h0 + d];  // 1 - nu
           // differences of IV = n.W between consecutive stencil cells
@@ -579,7 +584,7 @@ __device__ __forceinline__ void step3_tile(const StepArgs &p, int blk, int G, do
           const A D1 = (ick - Im1) - V[1] * invC;
           const A D2 = (Ip1 - ick) - V[2] * invC;
           A T;
-          if (mud > A(0)) {
+          if ((fl >> d) & 1u) {  // mu_d > 0
             const A Im2 = plane_value<S, A, PER>(p, r[2], s.idx[0], s.kind[0], 0, d, mc, mud);
             const A D0 = (Im1 - Im2) - V[0] * invC;
             const A qm = vl_half(D0, D1), q0 = vl_half(D1, D2);
