@@ -87,8 +87,9 @@ enum { RT_QUAD_GAUSS_LEGENDRE = 0, RT_QUAD_LEVEL_SYMMETRIC = 1 };
  * v + d4/(2 rho), and the system is solved again at that velocity from the
  * same right-hand side and T^n; the second solution is the step's.  The
  * scattering step keeps u.  rt_step runs both solves in its fused kernel
- * (about 1.2 times the single-solve step); rt_source_implicit runs the step
- * per cell.  RT_EUNSUPPORTED with RT_GAS_FEEDBACK. */
+ * (about 1.2 times the single-solve step), also with RT_GAS_FEEDBACK;
+ * rt_source_implicit runs the step per cell, and returns RT_EUNSUPPORTED
+ * when RT_GAS_FEEDBACK is set too. */
 #define RT_SECOND_ORDER 8u
 /* Number of entries of the totals vector. */
 #define RT_NTOT 12

@@ -369,7 +369,6 @@ int ctx_init_host(const rt_grid *g, const rt_angles *an, const rt_params *p, rt_
   if (!(p->c_reduced >= 0.0) || p->c_reduced > p->c) return RT_EINVAL;
   if (p->c_reduced > 0.0 && p->c_reduced < p->c && (p->flags & RT_ESTIMATE_V))
     return RT_EUNSUPPORTED;
-  if ((p->flags & RT_SECOND_ORDER) && (p->flags & RT_GAS_FEEDBACK)) return RT_EUNSUPPORTED;
 
   c->g = *g;
   c->p = *p;
@@ -770,6 +769,8 @@ int rt_source_implicit(rt_ctx *c, double dt, const rt_fields *f, const void *dF,
   if (!c || !fields_ok(f)) return RT_EINVAL;
   if (!c->I[0]) return RT_ESTATE;
   if ((c->p.flags & RT_GAS_FEEDBACK) && !c->shape.waves) return RT_EUNSUPPORTED;
+  // the second-order step from a given dF runs per cell, without feedback
+  if ((c->p.flags & RT_GAS_FEEDBACK) && c->shape.second) return RT_EUNSUPPORTED;
   if (!(dt > 0.0) || !std::isfinite(dt)) return RT_EINVAL;
   hipStream_t s = (hipStream_t)stream;
   int st = ensure_moments(c, s);

@@ -67,7 +67,7 @@ def _grid():
 
 @pytest.mark.parametrize("case", ["weights", "norm", "ndim", "bc", "c", "gamma", "cells",
                                   "angles", "c_reduced_above_c", "c_reduced_negative",
-                                  "c_reduced_with_estimate", "second_order_with_feedback"])
+                                  "c_reduced_with_estimate"])
 def test_create_validation_before_device(case):
     mu, w = rt.rt_quadrature(rt.RT_QUAD_LEVEL_SYMMETRIC, 4)
     g = _grid()
@@ -101,9 +101,6 @@ def test_create_validation_before_device(case):
         p = rt.make_params(1.0, 1.0, 5 / 3, 1.0, flags=0, c_reduced=-0.5)
     elif case == "c_reduced_with_estimate":
         p = rt.make_params(1.0, 1.0, 5 / 3, 1.0, flags=rt.RT_ESTIMATE_V, c_reduced=0.5)
-        expect = rt.RT_EUNSUPPORTED
-    elif case == "second_order_with_feedback":
-        p = rt.make_params(1.0, 1.0, 5 / 3, 1.0, flags=rt.RT_SECOND_ORDER | rt.RT_GAS_FEEDBACK)
         expect = rt.RT_EUNSUPPORTED
     with pytest.raises(rt.RTError) as ei:
         rt.rt_create(g, mu, w, p)

@@ -159,3 +159,40 @@ def test_with_reduced_speed_of_light(precision, tol):
         refmap = dict(E=ref.E, F=ref.F, T=ref.T)
     errs = {k: _nerr(st[k], v) for k, v in refmap.items()}
     assert max(errs.values()) <= tol, errs
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", TOL64), ("mixed", 1e-5)])
+def test_with_gas_feedback(precision, tol):
+    # both solves in the fused step, then the step's momentum change moves the
+    # flow (the oracle composes its second-order step with the same update);
+    # the next step's centred velocity starts from the moved flow
+    import oracle
+    wl = W.small_case(3, (9, 8, 7), ("ls", 6), seed=83, nsteps=5, vscale=0.05, kappa_a=2.0,
+                      kappa_s=1.0, rho_s=0.3, T_s=0.1, P=2.0)
+    ref = oracle.State(oracle.Problem(wl, feedback=True, second_order=True)).step(nsteps=5)
+    s = _solver(wl, precision=precision, feedback=True)
+    print(f"case {wl.name} second order with feedback, {precision}", flush=True)
+    s.step(5)
+    st = s.state()
+    status = s.status()
+    s.close()
+    assert status == 0
+    refmap = dict(I=ref.I, T=ref.T, E=ref.E, F=ref.F, P=ref.Pr, v=ref.v)
+    errs = {k: _nerr(st[k], r) for k, r in refmap.items()}
+    print(errs, flush=True)
+    assert max(errs.values()) <= tol, errs
+    # the flow moved and the case tells second order from the single solve
+    assert _nerr(st["v"], wl.v) > 1e-8
+    single = oracle.State(oracle.Problem(wl, feedback=True)).step(nsteps=5)
+    assert _nerr(ref.I, single.I) > 1e-6
+
+
+def test_unfused_second_order_with_feedback_is_rejected():
+    from paper_1403_6126_amd import rt
+    wl = W.small_case(3, (8, 7, 6), ("ls", 4), seed=84, vscale=0.05)
+    s = _solver(wl, feedback=True)
+    dF = s.transport()
+    with pytest.raises(rt.RTError) as ei:
+        s.source(dF)
+    assert ei.value.status == rt.RT_EUNSUPPORTED
+    s.close()
