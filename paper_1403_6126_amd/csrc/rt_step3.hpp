@@ -972,14 +972,15 @@ __device__ __forceinline__ void step3_tile(const StepArgs &p, int blk, int G, do
 
 // Order of the tiles over the blocks: 0 dispatch order, 1 XCD-contiguous,
 // 2 XCD slabs of z-planes with z fastest (slab_block), 3, 4, 5 the same in
-// sub-slabs of 4, 8, 2 planes.  FP64 (three 40 KB tiles of intensities per
-// CU in flight) takes sub-slabs of 4: 2.77 -> 2.72 ms on the 128^3 S8 box;
-// FP32 the same either way.
+// sub-slabs of 4, 8, 2 planes.  Both take sub-slabs of 4: on the 128^3 S8
+// box FP64 (three 40 KB tiles of intensities per CU in flight) 2.77 -> 2.72
+// ms with the fetched bytes 9.7 -> 5.1 GB, FP32 the same time with 4.0 ->
+// 2.3 GB fetched.
 #ifndef RT_BLOCK_ORDER_F64
 #define RT_BLOCK_ORDER_F64 3
 #endif
 #ifndef RT_BLOCK_ORDER_F32
-#define RT_BLOCK_ORDER_F32 2
+#define RT_BLOCK_ORDER_F32 3
 #endif
 
 template <typename S, typename A, int KA, int NG, bool PER, bool FUSED, bool SO = false>
