@@ -162,11 +162,14 @@ __device__ __forceinline__ S plane_buf_ld(const S *plane, unsigned idx) {
 }
 
 // Intensity at a stencil cell from the value raw read at its (clamped) cell
-// idx of the angle plane, with the ghost kinds.
+// idx of the angle plane, with the ghost kinds.  ghosts (wave-uniform): some
+// lane of the wave has a ghost cell along this axis; without any, the
+// per-lane kind tests are skipped by a scalar branch.
 template <typename S, typename A, bool PER>
 __device__ __forceinline__ A plane_value(const StepArgs &p, S raw, int idx, int kind, int side,
-                                         int d, int m, A mud) {
-  if (PER || kind == 0) return A(raw);
+                                         int d, int m, A mud, bool ghosts) {
+  if (PER || !ghosts) return A(raw);
+  if (kind == 0) return A(raw);
   if (kind == 1) return A(fixed_ghost(p, d, side, m, idx));
   const bool outgoing = side == 0 ? (mud < A(0)) : (mud > A(0));
   return outgoing ? A(raw) : A(0);
@@ -523,6 +526,9 @@ __device__ __forceinline__ void step3_tile(const StepArgs &p, int blk, int G, do
       if (CELL_EARLY && d == p.ndim - 1) cell_load();
       AxisData<A> s;
       axis_get<A, PER>(lds, d, s, lane);
+      // does any lane of the wave have a ghost cell along this axis
+      const bool ghosts =
+          !PER && __any(s.kind[0] | s.kind[1] | s.kind[2] | s.kind[3]) != 0;
       constexpr int UNR = sizeof(A) == 8 ? RT_UNROLL_F64 : RT_UNROLL_F32;
       // the plane reads of a slot: cells -1 and +1 and the far upwind cell
       // (-2 for mu_d > 0, else +2).  Those of the PF next slots of the axis
@@ -578,19 +584,19 @@ __device__ __forceinline__ void step3_tile(const StepArgs &p, int blk, int G, do
           A V[4];
 #pragma unroll
           for (int j = 0; j < 4; ++j) V[j] = n0 * s.dW[j][0] + n1 * s.dW[j][1] + n2 * s.dW[j][2];
-          const A Im1 = plane_value<S, A, PER>(p, r[0], s.idx[1], s.kind[1], 0, d, mc, mud);
-          const A Ip1 = plane_value<S, A, PER>(p, r[1], s.idx[2], s.kind[2], 1, d, mc, mud);
+          const A Im1 = plane_value<S, A, PER>(p, r[0], s.idx[1], s.kind[1], 0, d, mc, mud, ghosts);
+          const A Ip1 = plane_value<S, A, PER>(p, r[1], s.idx[2], s.kind[2], 1, d, mc, mud, ghosts);
           const A ick = IC_REG ? Ic[IC_REG ? k : 0] : A(r[3]);
           const A D1 = (ick - Im1) - V[1] * invC;
           const A D2 = (Ip1 - ick) - V[2] * invC;
           A T;
           if ((fl >> d) & 1u) {  // mu_d > 0
-            const A Im2 = plane_value<S, A, PER>(p, r[2], s.idx[0], s.kind[0], 0, d, mc, mud);
+            const A Im2 = plane_value<S, A, PER>(p, r[2], s.idx[0], s.kind[0], 0, d, mc, mud, ghosts);
             const A D0 = (Im1 - Im2) - V[0] * invC;
             const A qm = vl_half(D0, D1), q0 = vl_half(D1, D2);
             T = s.cbR * D2 + (s.caL + s.cbL) * D1 + h2 * (s.caR * q0 - s.caL * qm);
           } else {
-            const A Ip2 = plane_value<S, A, PER>(p, r[2], s.idx[3], s.kind[3], 1, d, mc, mud);
+            const A Ip2 = plane_value<S, A, PER>(p, r[2], s.idx[3], s.kind[3], 1, d, mc, mud, ghosts);
             const A D3 = (Ip2 - Ip1) - V[3] * invC;
             const A q0 = vl_half(D1, D2), qp = vl_half(D2, D3);
             T = (s.caR + s.cbR) * D2 + s.cbL * D1 - h2 * (s.caR * qp - s.caL * q0);
